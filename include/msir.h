@@ -1,0 +1,228 @@
+/*
+ * msir.h -- C ABI of the MI355X multistage mixed precision iterative refinement
+ * library (libmsir.so).
+ *
+ * The method is Algorithm 4 ("Multistage Iterative Refinement") of Oktay and
+ * Carson, "Multistage Mixed Precision Iterative Refinement": an LU factorization
+ * with partial pivoting in a low precision u_f is reused by a refinement loop
+ * whose residual is computed in u_r; the correction comes from triangular solves
+ * in u_f (SIR), from left-preconditioned GMRES with the preconditioned operator
+ * applied in u (SGMRES-IR, Algorithm 3) or in u^2 (GMRES-IR, Algorithm 2); the
+ * stopping criteria of Sec. 2.1.1 decide when to move to the next variant and,
+ * after GMRES-IR, to raise u_f and refactor.
+ *
+ * Conventions for every entry point:
+ *  - Matrices are column-major with an explicit leading dimension (LAPACK style).
+ *  - Array arguments named d* are DEVICE pointers on the handle's device; the
+ *    caller owns them.  Inputs are never modified.  Outputs are written only on
+ *    success (return value >= 0).
+ *  - Work is ordered on the handle's HIP stream; every call returns after its
+ *    results are complete (host-visible where they are host outputs).
+ *  - Return value: 0 success / converged; > 0 numerical outcome (MSIR_NOT_CONVERGED,
+ *    MSIR_SINGULAR); < 0 error: -k means argument k (1-based) is invalid,
+ *    MSIR_ERR_HIP a HIP runtime error, MSIR_ERR_ALLOC device memory could not be
+ *    obtained within the handle's budget.  msir_status_string() names each code.
+ *  - The library holds no global state besides the handles; distinct handles may
+ *    be used from distinct host threads.  One handle must not be used by two
+ *    threads at once.
+ */
+#ifndef MSIR_H
+#define MSIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Floating-point formats (Table 3; bf16 per Sec. 2.2; MSIR_DD = double-double,
+ * the stand-in for quadruple precision, unit roundoff 2^-106).                  */
+typedef enum { MSIR_FP16 = 0, MSIR_BF16 = 1, MSIR_FP32 = 2, MSIR_FP64 = 3, MSIR_DD = 4 } msir_prec;
+
+/* Convergence detection (Sec. 2.1.1).  ESTIMATE: 0 <= phi <= sqrt(n) u_x
+ * (eq. for the normwise error estimate).  BACKWARD: normwise backward error of
+ * the iterate (inf-norm, residual in u_r) <= tol_nbe, tested at every residual.
+ * TRUE: forward error (needs x_true) and normwise backward error <= the initial u,
+ * the protocol of the paper's experiments (Sec. 3).                             */
+typedef enum { MSIR_CONV_ESTIMATE = 0, MSIR_CONV_BACKWARD = 1, MSIR_CONV_TRUE = 2 } msir_conv;
+
+/* Scaling before a half-precision LU (Sec. 2.1.2).  AUTO: unscaled first, and
+ * if the factors hold Inf/NaN, retry with two-sided power-of-two equilibration
+ * plus a scalar mu.  ALWAYS: two-sided scaling from the start.  COLS: column
+ * equilibration plus mu from the start.  Only applied when u_f is fp16.        */
+typedef enum { MSIR_SCALE_NEVER = 0, MSIR_SCALE_AUTO = 1, MSIR_SCALE_ALWAYS = 2, MSIR_SCALE_COLS = 3 } msir_scale;
+
+/* Solver parameters: the inputs of Algorithm 4 plus the readings listed in the
+ * design notes.  Fill with msir_params_default() and override.                 */
+typedef struct {
+    msir_prec uf, u, ur;   /* initial (u_f, u, u_r); u in {FP32, FP64}; ur in {FP64, DD} */
+    msir_prec ux;          /* storage precision of x: FP64 (default) or = u (paper mode) */
+    int    i_max;          /* maximum refinement steps of each variant (>= 1)           */
+    double tau;            /* GMRES relative preconditioned residual tolerance (> 0);
+                              <= 0 selects 1e-6 for u = fp32 and 1e-10 for u = fp64   */
+    double rho_thresh;     /* stopping parameter rho_thresh in (0, 1): 0.5 cautious  */
+    double k_max;          /* GMRES iterations per step; <= 0 selects 0.1 n           */
+    int    restart;        /* GMRES restart length, 0 = none                          */
+    msir_conv conv;        /* convergence detection mode                              */
+    double tol_nbe;        /* tolerance of MSIR_CONV_BACKWARD                         */
+    msir_scale scaling;    /* Sec. 2.1.2 scaling policy                               */
+    int    nb;             /* LU panel width; 0 = automatic (see msir_nb_auto)        */
+    int    max_steps;      /* global cap on refinement steps (safety)                 */
+} msir_params;
+
+/* One refinement step (one residual + one correction), Alg. 4 loop body.       */
+typedef struct {
+    int level;              /* number of precision escalations so far            */
+    int uf, u, ur;          /* msir_prec values in force for this step           */
+    int stage;              /* 0 SIR, 1 SGMRES-IR, 2 GMRES-IR                     */
+    int iter;               /* step index within the variant (1-based)           */
+    int k_gmres;            /* GMRES iterations of this step, -1 for SIR          */
+    int counted;            /* 0 for a SIR step discarded by the Inf/NaN check    */
+    double z, v, rho_max, phi;  /* monitors of Sec. 2.1.1 (true correction)      */
+    double rnorm;           /* ||r||_inf of the iterate the step started from    */
+    double nbe;             /* its normwise backward error                       */
+    unsigned events;        /* MSIR_EV_* bits                                    */
+} msir_step;
+
+#define MSIR_EV_NAN_D     1u   /* non-finite correction                          */
+#define MSIR_EV_RESET_X0  2u   /* x reset to x0 (phi > phi_0)                    */
+#define MSIR_EV_SWITCH    4u   /* moved to the next variant                      */
+#define MSIR_EV_ESCALATE  8u   /* u_f raised and A refactored                    */
+#define MSIR_EV_SCALED   16u   /* the factorization in use is scaled             */
+#define MSIR_EV_NAN_X0   32u   /* x0 replaced by zero                            */
+#define MSIR_EV_CONVERGED 64u
+
+typedef struct {
+    int    cged;            /* Alg. 4 output flag                                */
+    int    status;          /* same code as the return value                     */
+    int    steps;           /* refinement steps performed (history length)       */
+    int    n_lu;            /* factorizations performed                          */
+    int    gmres_iters;     /* total GMRES iterations                            */
+    int    final_uf, final_u, final_ur;
+    double nbe;             /* final normwise backward error, residual in dd     */
+    double ferr;            /* final forward error (NaN without x_true)          */
+    double cbe;             /* final componentwise backward error                */
+    double t_factor_ms, t_refine_ms;   /* device time split (HIP events)         */
+} msir_result;
+
+typedef struct msir_handle msir_handle;
+
+/* Status codes */
+#define MSIR_OK               0
+#define MSIR_NOT_CONVERGED    1
+#define MSIR_SINGULAR         2
+#define MSIR_ERR_HIP       -100
+#define MSIR_ERR_ALLOC     -101
+#define MSIR_ERR_SIZE      -102   /* n outside [1, MSIR_MAX_N]                     */
+#define MSIR_MAX_N         8192   /* register-resident panel limit (see msir_nb_auto) */
+
+/* Create a handle on HIP device `device`.  `stream` is a hipStream_t (NULL: the
+ * null stream).  `hbm_budget_bytes` caps the workspace the handle may allocate
+ * (0: no cap).  Errors: -1 h NULL, -2 bad device, MSIR_ERR_HIP.                */
+int msir_create(msir_handle** h, int device, size_t hbm_budget_bytes, void* stream);
+/* Release the handle and its workspace (NULL is accepted).                      */
+int msir_destroy(msir_handle* h);
+/* Paper defaults: (fp16, fp32, fp64), ux fp64, i_max 10, tau auto, rho 0.5,
+ * k_max 0.1 n, restart 0, CONV_BACKWARD with tol 1e-15, SCALE_AUTO, nb auto.   */
+void msir_params_default(msir_params* p);
+/* Panel width used for an n x n factorization whose arithmetic is fp32 (fmt in
+ * {FP16, BF16, FP32}) or fp64 (FP64): the panel is held in registers of one
+ * compute unit, 64 (fp32) or 32 (fp64) values per thread over 1024 threads.    */
+int msir_nb_auto(int n, msir_prec fmt);
+/* Bytes of device workspace msir_solve needs for order n under params.          */
+size_t msir_workspace_bytes(int n, const msir_params* p);
+const char* msir_status_string(int status);
+
+/* ---- Whole solve: Algorithm 4 ------------------------------------------------
+ * Solve A x = b.  dA: n x n float64 (lda >= n).  db, dx: n float64.  dx_true:
+ * NULL or the exact solution (enables ferr and CONV_TRUE).  params: NULL for
+ * defaults.  out: NULL or result.  hist: NULL or caller host array of hist_cap
+ * steps; *hist_len (may be NULL) receives the number of steps performed (it may
+ * exceed hist_cap; only the first hist_cap are stored).
+ * Returns MSIR_OK (converged), MSIR_NOT_CONVERGED (precision ladder exhausted or
+ * max_steps reached; dx holds the last iterate), or an error (< 0).            */
+int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
+               const double* dx_true, const msir_params* params, msir_result* out,
+               msir_step* hist, int hist_cap, int* hist_len);
+
+/* nrhs right-hand sides sharing one factorization per precision level (the
+ * multi-RHS reading of Alg. 4: an independent controller per column; when a
+ * column escalates, the higher-precision factorization is computed once and
+ * reused by every column that reaches it).  dB, dX: n x nrhs column-major.
+ * outs: NULL or nrhs results.  Returns the worst status over the columns.      */
+int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda,
+                     const double* dB, int ldb, double* dX, int ldx,
+                     const msir_params* params, msir_result* outs);
+
+/* Independent systems of uneven sizes solved with one handle: system i has order
+ * n[i], matrix dA[i] (lda[i]), right-hand side db[i] and solution dx[i].  Host
+ * arrays of device pointers.  outs: NULL or count results.  Returns the worst
+ * status.                                                                        */
+int msir_solve_batched(msir_handle* h, int count, const int* n, const double* const* dA,
+                       const int* lda, const double* const* db, double* const* dx,
+                       const msir_params* params, msir_result* outs);
+
+/* ---- Steps of the hot path (each call is one row of Algorithm 4) -------------
+ * These are the building blocks msir_solve runs, exposed so each can be checked
+ * on its own.  Matrices of format f are stored as: FP16/BF16 uint16 bit
+ * patterns, FP32 float, FP64 double.                                             */
+
+/* Round dA (n x n float64) to format `f` into dW (ldw >= n), directly and with
+ * round-to-nearest-even (Alg. 4 first line: A held in u_f).  If scaling is
+ * non-NULL it holds host arrays R[n], S[n] and scaling[2n] = mu, and dW receives
+ * fl_f(mu R A S) (Sec. 2.1.2).  Returns 0 or < 0.                                 */
+int msir_convert(msir_handle* h, int n, const double* dA, int lda, msir_prec f,
+                 const double* R, const double* S, double mu, void* dW, int ldw);
+
+/* Compute the scaling of Sec. 2.1.2 for dA: R (rows; all ones when rows == 0), S,
+ * mu, written to host arrays R[n], S[n] and *mu.  f is the factor format.         */
+int msir_scaling(msir_handle* h, int n, const double* dA, int lda, msir_prec f, int rows,
+                 double* R, double* S, double* mu);
+
+/* LU with partial pivoting in place on dW (format f, n x n, ldw), panel width nb
+ * (0 = msir_nb_auto).  dipiv: n int32, LAPACK-style 0-based interchanges (rows j
+ * and dipiv[j] swapped at step j).  *info: 0, or k+1 for the first zero pivot
+ * column k.  Factors: unit lower L below the diagonal, U on and above, all in f,
+ * computed as described for the blocked model (panel in fp32 or fp64 registers,
+ * rank-1 updates by fused multiply-add, trailing update accumulated in fp32 on
+ * the matrix cores for fp16/bf16).                                               */
+int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, int nb, int* dipiv, int* info);
+
+/* Solve with stored factors: dy = mu S U^{-1} L^{-1} P R dt (Alg. 4 SIR solve and
+ * the GMRES preconditioner), every solution component rounded to `comp`:
+ * comp = f is the u_f-precision solve; comp in {FP32, FP64, DD} the operator
+ * precision p.  dt, dy: n float64 (for DD, dt and dy point to 2n doubles: hi then
+ * lo).  R, S: device arrays or NULL; mu scalar.  mode 0: exact row-by-row
+ * substitution inside diagonal blocks; mode 1: diagonal blocks applied through
+ * their float64 inverses (faster; differs by rounding).                          */
+int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, const int* dipiv,
+               const double* dR, const double* dS, double mu, msir_prec comp, int mode,
+               const double* dt, double* dy);
+
+/* Residual r = b - A x in ur (FP64 or DD), s = ||r||_inf, and the scaled residual
+ * r_hat = fl_u(r / s) (Alg. 4 residual line and Sec. 2.1.2).  drhat: n float64
+ * holding u values.  *s receives s (host).                                        */
+int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double* dx,
+                  const double* db, msir_prec ur, msir_prec u, double* drhat, double* s);
+
+/* One GMRES correction (Alg. 2 / Alg. 3): d solves M^{-1} A d = M^{-1} rhat with
+ * M = LU from msir_getrf, operator precision p (FP32: A rounded to fp32; FP64;
+ * DD), working precision u, tolerance tau, at most ceil(k_max) iterations, restart
+ * length restart (0 = none).  dd: n float64 (u values).  *k receives the number
+ * of iterations.  R, S, mu as for msir_getrs.                                     */
+int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, const void* dW,
+               int ldw, const int* dipiv, const double* dR, const double* dS, double mu,
+               const double* drhat, msir_prec u, msir_prec p, double tau, double k_max,
+               int restart, double* dd, int* k);
+
+/* Normwise and componentwise backward errors of x (Sec. 2, error measures), the
+ * residual formed in double-double: nbe = ||b-Ax||_inf/(||A||_inf ||x||_inf +
+ * ||b||_inf), cbe = max_i |b-Ax|_i / (|A||x| + |b|)_i.                           */
+int msir_backward_error(msir_handle* h, int n, const double* dA, int lda, const double* dx,
+                        const double* db, double* nbe, double* cbe);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MSIR_H */
