@@ -32,6 +32,12 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#if defined(__GNUC__) || defined(__clang__)
+#define MSIR_API __attribute__((visibility("default")))
+#else
+#define MSIR_API
+#endif
+
 #ifdef __cplusplus
 extern "C" {
 #endif
@@ -120,19 +126,19 @@ typedef struct msir_handle msir_handle;
 /* Create a handle on HIP device `device`.  `stream` is a hipStream_t (NULL: the
  * null stream).  `hbm_budget_bytes` caps the workspace the handle may allocate
  * (0: no cap).  Errors: -1 h NULL, -2 bad device, MSIR_ERR_HIP.                */
-int msir_create(msir_handle** h, int device, size_t hbm_budget_bytes, void* stream);
+MSIR_API int msir_create(msir_handle** h, int device, size_t hbm_budget_bytes, void* stream);
 /* Release the handle and its workspace (NULL is accepted).                      */
-int msir_destroy(msir_handle* h);
+MSIR_API int msir_destroy(msir_handle* h);
 /* Paper defaults: (fp16, fp32, fp64), ux fp64, i_max 10, tau auto, rho 0.5,
  * k_max 0.1 n, restart 0, CONV_BACKWARD with tol 1e-15, SCALE_AUTO, nb auto.   */
-void msir_params_default(msir_params* p);
+MSIR_API void msir_params_default(msir_params* p);
 /* Panel width used for an n x n factorization whose arithmetic is fp32 (fmt in
  * {FP16, BF16, FP32}) or fp64 (FP64): the panel is held in registers of one
  * compute unit, 64 (fp32) or 32 (fp64) values per thread over 1024 threads.    */
-int msir_nb_auto(int n, msir_prec fmt);
+MSIR_API int msir_nb_auto(int n, msir_prec fmt);
 /* Bytes of device workspace msir_solve needs for order n under params.          */
-size_t msir_workspace_bytes(int n, const msir_params* p);
-const char* msir_status_string(int status);
+MSIR_API size_t msir_workspace_bytes(int n, const msir_params* p);
+MSIR_API const char* msir_status_string(int status);
 
 /* ---- Whole solve: Algorithm 4 ------------------------------------------------
  * Solve A x = b.  dA: n x n float64 (lda >= n).  db, dx: n float64.  dx_true:
@@ -142,7 +148,7 @@ const char* msir_status_string(int status);
  * exceed hist_cap; only the first hist_cap are stored).
  * Returns MSIR_OK (converged), MSIR_NOT_CONVERGED (precision ladder exhausted or
  * max_steps reached; dx holds the last iterate), or an error (< 0).            */
-int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
+MSIR_API int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
                const double* dx_true, const msir_params* params, msir_result* out,
                msir_step* hist, int hist_cap, int* hist_len);
 
@@ -151,7 +157,7 @@ int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* d
  * column escalates, the higher-precision factorization is computed once and
  * reused by every column that reaches it).  dB, dX: n x nrhs column-major.
  * outs: NULL or nrhs results.  Returns the worst status over the columns.      */
-int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda,
+MSIR_API int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda,
                      const double* dB, int ldb, double* dX, int ldx,
                      const msir_params* params, msir_result* outs);
 
@@ -159,7 +165,7 @@ int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda,
  * n[i], matrix dA[i] (lda[i]), right-hand side db[i] and solution dx[i].  Host
  * arrays of device pointers.  outs: NULL or count results.  Returns the worst
  * status.                                                                        */
-int msir_solve_batched(msir_handle* h, int count, const int* n, const double* const* dA,
+MSIR_API int msir_solve_batched(msir_handle* h, int count, const int* n, const double* const* dA,
                        const int* lda, const double* const* db, double* const* dx,
                        const msir_params* params, msir_result* outs);
 
@@ -172,12 +178,12 @@ int msir_solve_batched(msir_handle* h, int count, const int* n, const double* co
  * round-to-nearest-even (Alg. 4 first line: A held in u_f).  If scaling is
  * non-NULL it holds host arrays R[n], S[n] and scaling[2n] = mu, and dW receives
  * fl_f(mu R A S) (Sec. 2.1.2).  Returns 0 or < 0.                                 */
-int msir_convert(msir_handle* h, int n, const double* dA, int lda, msir_prec f,
+MSIR_API int msir_convert(msir_handle* h, int n, const double* dA, int lda, msir_prec f,
                  const double* R, const double* S, double mu, void* dW, int ldw);
 
 /* Compute the scaling of Sec. 2.1.2 for dA: R (rows; all ones when rows == 0), S,
  * mu, written to host arrays R[n], S[n] and *mu.  f is the factor format.         */
-int msir_scaling(msir_handle* h, int n, const double* dA, int lda, msir_prec f, int rows,
+MSIR_API int msir_scaling(msir_handle* h, int n, const double* dA, int lda, msir_prec f, int rows,
                  double* R, double* S, double* mu);
 
 /* LU with partial pivoting in place on dW (format f, n x n, ldw), panel width nb
@@ -187,7 +193,7 @@ int msir_scaling(msir_handle* h, int n, const double* dA, int lda, msir_prec f, 
  * computed as described for the blocked model (panel in fp32 or fp64 registers,
  * rank-1 updates by fused multiply-add, trailing update accumulated in fp32 on
  * the matrix cores for fp16/bf16).                                               */
-int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, int nb, int* dipiv, int* info);
+MSIR_API int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, int nb, int* dipiv, int* info);
 
 /* Solve with stored factors: dy = mu S U^{-1} L^{-1} P R dt (Alg. 4 SIR solve and
  * the GMRES preconditioner), every solution component rounded to `comp`:
@@ -196,14 +202,14 @@ int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, int nb, in
  * lo).  R, S: device arrays or NULL; mu scalar.  mode 0: exact row-by-row
  * substitution inside diagonal blocks; mode 1: diagonal blocks applied through
  * their float64 inverses (faster; differs by rounding).                          */
-int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, const int* dipiv,
+MSIR_API int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, const int* dipiv,
                const double* dR, const double* dS, double mu, msir_prec comp, int mode,
                const double* dt, double* dy);
 
 /* Residual r = b - A x in ur (FP64 or DD), s = ||r||_inf, and the scaled residual
  * r_hat = fl_u(r / s) (Alg. 4 residual line and Sec. 2.1.2).  drhat: n float64
  * holding u values.  *s receives s (host).                                        */
-int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double* dx,
+MSIR_API int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double* dx,
                   const double* db, msir_prec ur, msir_prec u, double* drhat, double* s);
 
 /* One GMRES correction (Alg. 2 / Alg. 3): d solves M^{-1} A d = M^{-1} rhat with
@@ -211,7 +217,7 @@ int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double
  * DD), working precision u, tolerance tau, at most ceil(k_max) iterations, restart
  * length restart (0 = none).  dd: n float64 (u values).  *k receives the number
  * of iterations.  R, S, mu as for msir_getrs.                                     */
-int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, const void* dW,
+MSIR_API int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, const void* dW,
                int ldw, const int* dipiv, const double* dR, const double* dS, double mu,
                const double* drhat, msir_prec u, msir_prec p, double tau, double k_max,
                int restart, double* dd, int* k);
@@ -219,7 +225,7 @@ int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, co
 /* Normwise and componentwise backward errors of x (Sec. 2, error measures), the
  * residual formed in double-double: nbe = ||b-Ax||_inf/(||A||_inf ||x||_inf +
  * ||b||_inf), cbe = max_i |b-Ax|_i / (|A||x| + |b|)_i.                           */
-int msir_backward_error(msir_handle* h, int n, const double* dA, int lda, const double* dx,
+MSIR_API int msir_backward_error(msir_handle* h, int n, const double* dA, int lda, const double* dx,
                         const double* db, double* nbe, double* cbe);
 
 #ifdef __cplusplus

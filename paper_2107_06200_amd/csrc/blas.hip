@@ -1,0 +1,442 @@
+// Memory-bound kernels of the refinement loop (gfx950).
+//
+//  * conversion of A into the factor format u_f with optional power-of-two
+//    scaling (Alg. 4 first line; Sec. 2.1.2) and into the fp32 copy used by
+//    the SGMRES-IR operator (Alg. 3, products "computed at precision u")
+//  * the scaling factors of Sec. 2.1.2 (row/column equilibration, mu)
+//  * the residual r = b - A x in u_r = fp64 or double-double (Alg. 4 residual
+//    line), its inf-norm s and the scaled residual fl_u(r/s)
+//  * A v in precision p (fp32 copy, fp64, double-double) for GMRES (Alg. 2/3)
+//  * the update x <- fl(x + fl(s d)) and the norms feeding the monitors of
+//    Sec. 2.1.1
+//
+// All of them stream a column-major matrix once: thread = row, consecutive
+// threads read consecutive addresses of a column; the column range is split
+// over a second grid dimension so that a launch has many more workgroups than
+// the 256 compute units.  Partial sums are combined in a fixed order by the
+// last workgroup to finish (no floating-point atomics), so results are
+// reproducible run to run.
+#include "common.hpp"
+#include "msir_internal.hpp"
+
+namespace msir {
+
+constexpr int RT = 256;  // rows per workgroup (one per thread)
+
+// ------------------------------------------------------------------ conversion
+template <int P>
+__global__ __launch_bounds__(256) void k_convert(int n, const double* __restrict__ A, int lda,
+                                                 const double* __restrict__ R, const double* __restrict__ S,
+                                                 double mu, typename Store<P>::T* __restrict__ W, int ldw) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  const int j = blockIdx.y;
+  if (i >= n) return;
+  double a = A[(size_t)j * lda + i];
+  if (R) a = (mu * (R[i] * a)) * S[j];
+  W[(size_t)j * ldw + i] = Store<P>::from_d(a);
+}
+
+int convert(Ctx& c, int n, const double* A, int lda, int prec, const double* R, const double* S, double mu,
+            void* W, int ldw) {
+  dim3 g((n + 255) / 256, n);
+  switch (prec) {
+    case P_FP16: k_convert<P_FP16><<<g, 256, 0, c.stream>>>(n, A, lda, R, S, mu, (uint16_t*)W, ldw); break;
+    case P_BF16: k_convert<P_BF16><<<g, 256, 0, c.stream>>>(n, A, lda, R, S, mu, (uint16_t*)W, ldw); break;
+    case P_FP32: k_convert<P_FP32><<<g, 256, 0, c.stream>>>(n, A, lda, R, S, mu, (float*)W, ldw); break;
+    case P_FP64: k_convert<P_FP64><<<g, 256, 0, c.stream>>>(n, A, lda, R, S, mu, (double*)W, ldw); break;
+    default: return -5;
+  }
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+// ------------------------------------------------------------------ scaling
+// Power of two 2^-e with 2^(e-1) <= m < 2^e; 1 for m == 0 or non-finite m.
+__device__ __forceinline__ double pow2_equilibrator(double m) {
+  if (!(m > 0.0) || !__builtin_isfinite(m)) return 1.0;
+  int e;
+  (void)frexp(m, &e);
+  return ldexp(1.0, -e);
+}
+
+// row maxima of |A| (rows == 1) -> R, else R = 1
+__global__ __launch_bounds__(256) void k_rowmax(int n, const double* __restrict__ A, int lda, int rows,
+                                                double* __restrict__ R) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  if (!rows) { R[i] = 1.0; return; }
+  double m = 0.0;
+  for (int j = 0; j < n; ++j) m = fmax(m, fabs(A[(size_t)j * lda + i]));
+  R[i] = pow2_equilibrator(m);
+}
+
+// column maxima of |R A| -> S, and per-column max of |R A S| into colmax
+__global__ __launch_bounds__(256) void k_colscale(int n, const double* __restrict__ A, int lda,
+                                                  const double* __restrict__ R, double* __restrict__ S,
+                                                  double* __restrict__ colmax) {
+  const int j = blockIdx.x;
+  __shared__ double sh[4];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, fabs(R[i] * A[(size_t)j * lda + i]));
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    double s = pow2_equilibrator(t);
+    S[j] = s;
+    colmax[j] = t * s;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mu(int n, const double* __restrict__ colmax, double xmax, double theta,
+                                            double* __restrict__ mu_out) {
+  __shared__ double sh[4];
+  double m = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) m = fmax(m, colmax[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+    double mu = 1.0;
+    if (t > 0.0 && __builtin_isfinite(t)) {
+      int e;
+      (void)frexp(theta * xmax / t, &e);
+      mu = ldexp(1.0, e - 1);
+    }
+    *mu_out = mu;
+  }
+}
+
+int scaling(Ctx& c, int n, const double* A, int lda, int prec, int rows, double* dR, double* dS, double* dmu,
+            double* dtmp) {
+  const double xmax = prec == P_FP16 ? 65504.0 : (prec == P_BF16 ? 3.3895313892515355e38 : 3.4028234663852886e38);
+  k_rowmax<<<(n + 255) / 256, 256, 0, c.stream>>>(n, A, lda, rows, dR);
+  k_colscale<<<n, 256, 0, c.stream>>>(n, A, lda, dR, dS, dtmp);
+  k_mu<<<1, 256, 0, c.stream>>>(n, dtmp, xmax, 0.0625, dmu);
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+// ------------------------------------------------------------------ last-block combine
+// Each block writes its partial; the last block to arrive (device-scope counter)
+// sees all partials.  The counter is reset by that block for the next launch.
+__device__ __forceinline__ bool arrive_last(unsigned* counter) {
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x * gridDim.y - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+// ------------------------------------------------------------------ GEMV partials
+// y_part[split][i] = sum_{j in split} A[i, j] x[j]   (TA: double or float matrix;
+// accumulation in double).  DD: hi/lo partials.
+template <typename TA, bool DD>
+__global__ __launch_bounds__(RT) void k_gemv_part(int n, const TA* __restrict__ A, int lda,
+                                                  const double* __restrict__ x, int chunk,
+                                                  double* __restrict__ part_hi, double* __restrict__ part_lo,
+                                                  const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = blockIdx.x * RT + threadIdx.x;
+  const int s = blockIdx.y;
+  const int j0 = s * chunk;
+  const int j1 = min(n, j0 + chunk);
+  if (i >= n) return;
+  const TA* a = A + (size_t)j0 * lda + i;
+  if (!DD) {
+    double acc0 = 0.0, acc1 = 0.0;
+    int j = j0;
+    for (; j + 1 < j1; j += 2) {
+      acc0 = __fma_rn((double)a[0], x[j], acc0);
+      acc1 = __fma_rn((double)a[lda], x[j + 1], acc1);
+      a += 2 * (size_t)lda;
+    }
+    if (j < j1) acc0 = __fma_rn((double)a[0], x[j], acc0);
+    part_hi[(size_t)s * n + i] = __dadd_rn(acc0, acc1);
+  } else {
+    double h = 0.0, l = 0.0;
+    for (int j = j0; j < j1; ++j) {
+      double p, e;
+      two_prod((double)a[0], x[j], p, e);
+      dd_add(h, l, p, e, h, l);
+      a += lda;
+    }
+    part_hi[(size_t)s * n + i] = h;
+    part_lo[(size_t)s * n + i] = l;
+  }
+}
+
+// Combine partials: out = b - sum (resid) or out = sum; optionally the block max of |out|.
+// Residual mode writes r (hi[, lo]) and, in the last block, s = max|r| and rhat = fl_u(r/s).
+template <bool DD>
+__global__ __launch_bounds__(RT) void k_resid_finish(int n, int nsplit, const double* __restrict__ part_hi,
+                                                     const double* __restrict__ part_lo, const double* __restrict__ b,
+                                                     double* __restrict__ r_hi, double* __restrict__ r_lo,
+                                                     double* __restrict__ blockmax, unsigned* counter, int u,
+                                                     double* __restrict__ rhat, double* __restrict__ s_out) {
+  const int i = blockIdx.x * RT + threadIdx.x;
+  double m = 0.0;
+  bool nan = false;
+  if (i < n) {
+    if (!DD) {
+      double acc = 0.0;
+      for (int s = 0; s < nsplit; ++s) acc = __dadd_rn(acc, part_hi[(size_t)s * n + i]);
+      double r = __dsub_rn(b[i], acc);
+      r_hi[i] = r;
+      m = fabs(r);
+      nan = !(m == m);
+    } else {
+      double h = b[i], l = 0.0;
+      for (int s = 0; s < nsplit; ++s) dd_add(h, l, -part_hi[(size_t)s * n + i], -part_lo[(size_t)s * n + i], h, l);
+      r_hi[i] = h;
+      r_lo[i] = l;
+      double v = __dadd_rn(h, l);
+      m = fabs(v);
+      nan = !(m == m);
+    }
+  }
+  __shared__ double sh[RT / 64];
+  __shared__ int shn[RT / 64];
+  double wm = wave_max(m);
+  int wn = wave_or(nan ? 1 : 0);
+  if ((threadIdx.x & 63) == 0) { sh[threadIdx.x >> 6] = wm; shn[threadIdx.x >> 6] = wn; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0; int tn = 0;
+    for (int w = 0; w < RT / 64; ++w) { t = fmax(t, sh[w]); tn |= shn[w]; }
+    blockmax[blockIdx.x] = tn ? __builtin_nan("") : t;
+  }
+  if (!arrive_last(counter)) return;
+  // last block: s = max over blocks (NaN if any NaN), then rhat for all rows
+  __shared__ double s_sh;
+  if (threadIdx.x == 0) {
+    double t = 0.0; bool tn = false;
+    for (int k = 0; k < (int)gridDim.x; ++k) {
+      double v = __hip_atomic_load(&blockmax[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!(v == v)) tn = true; else t = fmax(t, v);
+    }
+    s_sh = tn ? __builtin_nan("") : t;
+    *s_out = s_sh;
+    *counter = 0u;
+  }
+  __syncthreads();
+  const double s = s_sh;
+  if (rhat) {
+    for (int k = threadIdx.x; k < n; k += RT) {
+      double q;
+      if (!DD) q = __hip_atomic_load(&r_hi[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / s;
+      else q = __dadd_rn(__hip_atomic_load(&r_hi[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / s,
+                         __hip_atomic_load(&r_lo[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / s);
+      rhat[k] = round_to(q, u);
+    }
+  }
+}
+
+static int nsplit_for(int n) {
+  // enough workgroups to fill the chip: rows/256 x splits >= ~1024
+  int rb = (n + RT - 1) / RT;
+  int s = (1024 + rb - 1) / rb;
+  int maxs = (n + 31) / 32;     // at least 32 columns per split
+  if (s > maxs) s = maxs;
+  if (s < 1) s = 1;
+  return s;
+}
+
+int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
+             double* rhat, double* s_dev) {
+  const int ns = nsplit_for(n);
+  const int chunk = (n + ns - 1) / ns;
+  const int rb = (n + RT - 1) / RT;
+  double* ph = c.ws_part_hi(ns * (size_t)n);
+  double* pl = c.ws_part_lo(ns * (size_t)n);
+  double* rh = c.ws_r_hi(n);
+  double* rl = c.ws_r_lo(n);
+  if (!ph || !pl || !rh || !rl) return MSIR_ERR_ALLOC;
+  dim3 g(rb, ns);
+  if (ur == P_DD) {
+    k_gemv_part<double, true><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, nullptr);
+    k_resid_finish<true><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
+  } else {
+    k_gemv_part<double, false><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, nullptr);
+    k_resid_finish<false><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
+  }
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+// ------------------------------------------------------------------ A v in precision p
+template <bool DD>
+__global__ __launch_bounds__(RT) void k_matvec_finish(int n, int nsplit, const double* __restrict__ part_hi,
+                                                      const double* __restrict__ part_lo, int p,
+                                                      double* __restrict__ y_hi, double* __restrict__ y_lo,
+                                                      const int* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = blockIdx.x * RT + threadIdx.x;
+  if (i >= n) return;
+  if (!DD) {
+    double acc = 0.0;
+    for (int s = 0; s < nsplit; ++s) acc = __dadd_rn(acc, part_hi[(size_t)s * n + i]);
+    y_hi[i] = round_to(acc, p);
+  } else {
+    double h = 0.0, l = 0.0;
+    for (int s = 0; s < nsplit; ++s) dd_add(h, l, part_hi[(size_t)s * n + i], part_lo[(size_t)s * n + i], h, l);
+    y_hi[i] = h;
+    y_lo[i] = l;
+  }
+}
+
+// y = A v with p in {FP32 (Au = fp32 copy of A), FP64, DD}; v holds values in u (float64 array).
+int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
+           double* y_hi, double* y_lo, const int* skip) {
+  const int ns = nsplit_for(n);
+  const int chunk = (n + ns - 1) / ns;
+  const int rb = (n + RT - 1) / RT;
+  double* ph = c.ws_part_hi(ns * (size_t)n);
+  double* pl = c.ws_part_lo(ns * (size_t)n);
+  if (!ph || !pl) return MSIR_ERR_ALLOC;
+  dim3 g(rb, ns);
+  if (p == P_FP32) {
+    k_gemv_part<float, false><<<g, RT, 0, c.stream>>>(n, Au, ldau, v, chunk, ph, pl, skip);
+    k_matvec_finish<false><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_FP32, y_hi, y_lo, skip);
+  } else if (p == P_FP64) {
+    k_gemv_part<double, false><<<g, RT, 0, c.stream>>>(n, A, lda, v, chunk, ph, pl, skip);
+    k_matvec_finish<false><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_FP64, y_hi, y_lo, skip);
+  } else {
+    k_gemv_part<double, true><<<g, RT, 0, c.stream>>>(n, A, lda, v, chunk, ph, pl, skip);
+    k_matvec_finish<true><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_DD, y_hi, y_lo, skip);
+  }
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+// ------------------------------------------------------------------ norms of A and b
+__global__ __launch_bounds__(RT) void k_rowabs_part(int n, const double* __restrict__ A, int lda, int chunk,
+                                                    double* __restrict__ part) {
+  const int i = blockIdx.x * RT + threadIdx.x;
+  const int s = blockIdx.y;
+  if (i >= n) return;
+  const int j0 = s * chunk, j1 = min(n, j0 + chunk);
+  double acc = 0.0;
+  for (int j = j0; j < j1; ++j) acc = __dadd_rn(acc, fabs(A[(size_t)j * lda + i]));
+  part[(size_t)s * n + i] = acc;
+}
+
+// out[0] = ||A||_inf (row sums in split order), out[1] = ||b||_inf
+__global__ __launch_bounds__(RT) void k_norms_finish(int n, int ns, const double* __restrict__ part,
+                                                     const double* __restrict__ b, double* __restrict__ bm,
+                                                     unsigned* counter, double* __restrict__ out) {
+  const int i = blockIdx.x * RT + threadIdx.x;
+  double ra = 0.0, bb = 0.0;
+  if (i < n) {
+    for (int s = 0; s < ns; ++s) ra = __dadd_rn(ra, part[(size_t)s * n + i]);
+    if (b) bb = fabs(b[i]);
+  }
+  __shared__ double sh[2][RT / 64];
+  ra = wave_max(ra); bb = wave_max(bb);
+  if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = ra; sh[1][threadIdx.x >> 6] = bb; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, c2 = 0;
+    for (int k = 0; k < RT / 64; ++k) { a = fmax(a, sh[0][k]); c2 = fmax(c2, sh[1][k]); }
+    bm[2 * blockIdx.x] = a; bm[2 * blockIdx.x + 1] = c2;
+  }
+  if (!arrive_last(counter)) return;
+  if (threadIdx.x == 0) {
+    double a = 0, c2 = 0;
+    for (int k = 0; k < (int)gridDim.x; ++k) {
+      a = fmax(a, __hip_atomic_load(&bm[2 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      c2 = fmax(c2, __hip_atomic_load(&bm[2 * k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    out[0] = a; out[1] = c2;
+    *counter = 0u;
+  }
+}
+
+int norms(Ctx& c, int n, const double* A, int lda, const double* b, double* out_dev) {
+  const int ns = nsplit_for(n);
+  const int chunk = (n + ns - 1) / ns;
+  const int rb = (n + RT - 1) / RT;
+  double* ph = c.ws_part_hi(ns * (size_t)n);
+  double* bm = c.ws_mon_part(2 * (size_t)rb);
+  if (!ph || !bm) return MSIR_ERR_ALLOC;
+  k_rowabs_part<<<dim3(rb, ns), RT, 0, c.stream>>>(n, A, lda, chunk, ph);
+  k_norms_finish<<<rb, RT, 0, c.stream>>>(n, ns, ph, b, bm, c.counter, out_dev);
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+// ------------------------------------------------------------------ componentwise denominators
+// den_part[split][i] = sum_{j in split} |A_ij| |x_j|
+__global__ __launch_bounds__(RT) void k_absgemv_part(int n, const double* __restrict__ A, int lda,
+                                                     const double* __restrict__ x, int chunk,
+                                                     double* __restrict__ part) {
+  const int i = blockIdx.x * RT + threadIdx.x;
+  const int s = blockIdx.y;
+  if (i >= n) return;
+  const int j0 = s * chunk, j1 = min(n, j0 + chunk);
+  double acc = 0.0;
+  for (int j = j0; j < j1; ++j) acc = __fma_rn(fabs(A[(size_t)j * lda + i]), fabs(x[j]), acc);
+  part[(size_t)s * n + i] = acc;
+}
+
+// errors: out[0] = max|r_i| (dd residual), out[1] = max_i |r_i| / (|A||x| + |b|)_i
+__global__ __launch_bounds__(RT) void k_errors_finish(int n, int ns, const double* __restrict__ den_part,
+                                                      const double* __restrict__ r_hi, const double* __restrict__ r_lo,
+                                                      const double* __restrict__ b, double* __restrict__ bm,
+                                                      unsigned* counter, double* __restrict__ out) {
+  const int i = blockIdx.x * RT + threadIdx.x;
+  double rm = 0.0, cb = 0.0;
+  if (i < n) {
+    double den = 0.0;
+    for (int s = 0; s < ns; ++s) den = __dadd_rn(den, den_part[(size_t)s * n + i]);
+    den = __dadd_rn(den, fabs(b[i]));
+    double r = fabs(__dadd_rn(r_hi[i], r_lo[i]));
+    rm = r;
+    cb = den > 0.0 ? r / den : (r > 0.0 ? __builtin_inf() : 0.0);
+  }
+  __shared__ double sh[2][RT / 64];
+  rm = wave_max(rm); cb = wave_max(cb);
+  if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = rm; sh[1][threadIdx.x >> 6] = cb; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, c2 = 0;
+    for (int k = 0; k < RT / 64; ++k) { a = fmax(a, sh[0][k]); c2 = fmax(c2, sh[1][k]); }
+    bm[2 * blockIdx.x] = a; bm[2 * blockIdx.x + 1] = c2;
+  }
+  if (!arrive_last(counter)) return;
+  if (threadIdx.x == 0) {
+    double a = 0, c2 = 0;
+    for (int k = 0; k < (int)gridDim.x; ++k) {
+      a = fmax(a, __hip_atomic_load(&bm[2 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+      c2 = fmax(c2, __hip_atomic_load(&bm[2 * k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+    }
+    out[0] = a; out[1] = c2;
+    *counter = 0u;
+  }
+}
+
+int backward_errors(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, double* out_dev) {
+  // dd residual into r_hi/r_lo (rhat not needed), then |A||x| partials
+  double* sdev = c.scratch_scalar(1);
+  int rc = residual(c, n, A, lda, x, b, P_DD, P_FP64, nullptr, sdev);
+  if (rc) return rc;
+  const int ns = nsplit_for(n);
+  const int chunk = (n + ns - 1) / ns;
+  const int rb = (n + RT - 1) / RT;
+  double* ph = c.ws_part_hi(ns * (size_t)n);
+  double* bm = c.ws_mon_part(2 * (size_t)rb);
+  if (!ph || !bm) return MSIR_ERR_ALLOC;
+  k_absgemv_part<<<dim3(rb, ns), RT, 0, c.stream>>>(n, A, lda, x, chunk, ph);
+  k_errors_finish<<<rb, RT, 0, c.stream>>>(n, ns, ph, c.ws_r_hi(n), c.ws_r_lo(n), b, bm, c.counter, out_dev);
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+}  // namespace msir

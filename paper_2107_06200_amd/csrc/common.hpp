@@ -1,0 +1,192 @@
+// Device and host helpers shared by the MSIR kernels (gfx950 / CDNA4).
+//
+// Rounding: every conversion into a narrower format is a single IEEE
+// round-to-nearest-even of the exact source value (Table 3 formats; bf16 of
+// Sec. 2.2).  float64 -> fp16/bf16 goes through a round-to-odd float32
+// intermediate, which makes the second rounding exact (24 >= 11 + 2 bits).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <math.h>
+
+#define MSIR_WAVE 64
+
+#define HIP_CHECK(expr)                                                      \
+  do {                                                                       \
+    hipError_t _e = (expr);                                                  \
+    if (_e != hipSuccess) {                                                  \
+      msir_set_error(hipGetErrorString(_e), __FILE__, __LINE__);             \
+      return MSIR_ERR_HIP;                                                   \
+    }                                                                        \
+  } while (0)
+
+void msir_set_error(const char* what, const char* file, int line);
+
+namespace msir {
+
+// precision codes (same values as msir_prec)
+enum Prec : int { P_FP16 = 0, P_BF16 = 1, P_FP32 = 2, P_FP64 = 3, P_DD = 4 };
+
+// ---------------------------------------------------------------- rounding
+__device__ __forceinline__ float f64_to_f32_rto(double x) {
+  float f = (float)x;  // RNE
+  if (__builtin_isfinite(f) && (double)f != x) {
+    uint32_t b = __float_as_uint(f);
+    if ((b & 1u) == 0u) {
+      // even neighbour chosen: the odd one lies on x's side of f
+      if (fabs(x) > fabs((double)f)) b += 1u; else b -= 1u;
+      f = __uint_as_float(b);
+    }
+  }
+  return f;
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
+  uint32_t b = __float_as_uint(f);
+  if ((b & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((b >> 16) | 0x40u);  // quiet NaN
+  uint32_t lsb = (b >> 16) & 1u;
+  b += 0x7fffu + lsb;
+  return (uint16_t)(b >> 16);
+}
+
+__device__ __forceinline__ float bf16_bits_to_f32(uint16_t h) {
+  return __uint_as_float(((uint32_t)h) << 16);
+}
+
+__device__ __forceinline__ uint16_t f32_to_f16_bits(float f) {
+  _Float16 h = (_Float16)f;  // v_cvt_f16_f32, RNE
+  return __builtin_bit_cast(uint16_t, h);
+}
+
+__device__ __forceinline__ float f16_bits_to_f32(uint16_t h) {
+  return (float)__builtin_bit_cast(_Float16, h);
+}
+
+__device__ __forceinline__ uint16_t f64_to_f16_bits(double x) { return f32_to_f16_bits(f64_to_f32_rto(x)); }
+__device__ __forceinline__ uint16_t f64_to_bf16_bits(double x) { return f32_to_bf16_bits(f64_to_f32_rto(x)); }
+
+// Round a float64 value to format p, returned as float64 (DD/FP64: unchanged).
+__device__ __forceinline__ double round_to(double x, int p) {
+  switch (p) {
+    case P_FP16: return (double)f16_bits_to_f32(f64_to_f16_bits(x));
+    case P_BF16: return (double)bf16_bits_to_f32(f64_to_bf16_bits(x));
+    case P_FP32: return (double)(float)x;
+    default: return x;
+  }
+}
+
+// ---------------------------------------------------------------- storage traits
+// Storage of a factor matrix in format P.
+template <int P> struct Store;
+template <> struct Store<P_FP16> {
+  typedef uint16_t T;
+  __device__ static float to_f(T v) { return f16_bits_to_f32(v); }
+  __device__ static double to_d(T v) { return (double)f16_bits_to_f32(v); }
+  __device__ static T from_f(float x) { return f32_to_f16_bits(x); }
+  __device__ static T from_d(double x) { return f64_to_f16_bits(x); }
+};
+template <> struct Store<P_BF16> {
+  typedef uint16_t T;
+  __device__ static float to_f(T v) { return bf16_bits_to_f32(v); }
+  __device__ static double to_d(T v) { return (double)bf16_bits_to_f32(v); }
+  __device__ static T from_f(float x) { return f32_to_bf16_bits(x); }
+  __device__ static T from_d(double x) { return f64_to_bf16_bits(x); }
+};
+template <> struct Store<P_FP32> {
+  typedef float T;
+  __device__ static float to_f(T v) { return v; }
+  __device__ static double to_d(T v) { return (double)v; }
+  __device__ static T from_f(float x) { return x; }
+  __device__ static T from_d(double x) { return (float)x; }
+};
+template <> struct Store<P_FP64> {
+  typedef double T;
+  __device__ static float to_f(T v) { return (float)v; }
+  __device__ static double to_d(T v) { return v; }
+  __device__ static T from_f(float x) { return (double)x; }
+  __device__ static T from_d(double x) { return x; }
+};
+
+// ---------------------------------------------------------------- double-double
+// Error-free transformations (Knuth TwoSum; TwoProduct by fused multiply-add).
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = __dadd_rn(a, b);
+  double bb = __dsub_rn(s, a);
+  e = __dadd_rn(__dsub_rn(a, __dsub_rn(s, bb)), __dsub_rn(b, bb));
+}
+__device__ __forceinline__ void quick_two_sum(double a, double b, double& s, double& e) {
+  s = __dadd_rn(a, b);
+  e = __dsub_rn(b, __dsub_rn(s, a));
+}
+__device__ __forceinline__ void two_prod(double a, double b, double& p, double& e) {
+  p = __dmul_rn(a, b);
+  e = __fma_rn(a, b, -p);
+}
+// (ah,al) + (bh,bl), accurate version
+__device__ __forceinline__ void dd_add(double ah, double al, double bh, double bl, double& sh, double& sl) {
+  double s, e, t, f;
+  two_sum(ah, bh, s, e);
+  two_sum(al, bl, t, f);
+  e = __dadd_rn(e, t);
+  quick_two_sum(s, e, s, e);
+  e = __dadd_rn(e, f);
+  quick_two_sum(s, e, sh, sl);
+}
+// (ah,al) * b
+__device__ __forceinline__ void dd_mul_d(double ah, double al, double b, double& ph, double& pl) {
+  double p, e;
+  two_prod(ah, b, p, e);
+  e = __fma_rn(al, b, e);
+  quick_two_sum(p, e, ph, pl);
+}
+// (ah,al) / b
+__device__ __forceinline__ void dd_div_d(double ah, double al, double b, double& qh, double& ql) {
+  double q1 = ah / b;
+  double ph, pl;
+  dd_mul_d(b, 0.0, q1, ph, pl);
+  double rh, rl;
+  dd_add(ah, al, -ph, -pl, rh, rl);
+  double q2 = rh / b;
+  dd_mul_d(b, 0.0, q2, ph, pl);
+  dd_add(rh, rl, -ph, -pl, rh, rl);
+  double q3 = rh / b;
+  double s, e;
+  quick_two_sum(q1, q2, s, e);
+  double t, f;
+  two_sum(s, q3, t, f);
+  f = __dadd_rn(f, e);
+  quick_two_sum(t, f, qh, ql);
+}
+
+// ---------------------------------------------------------------- wave reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = __dadd_rn(v, __shfl_xor(v, o, MSIR_WAVE));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, MSIR_WAVE));
+  return v;
+}
+__device__ __forceinline__ int wave_or(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, MSIR_WAVE);
+  return v;
+}
+
+// Block-wide sum of a double over blockDim.x threads (multiple of 64), deterministic order.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x / MSIR_WAVE, l = threadIdx.x % MSIR_WAVE;
+  __syncthreads();
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double r = 0.0;
+#pragma unroll
+  for (int i = 0; i < NT / MSIR_WAVE; ++i) r = __dadd_rn(r, sh[i]);
+  return r;
+}
+
+}  // namespace msir

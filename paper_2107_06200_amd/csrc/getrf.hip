@@ -1,0 +1,397 @@
+// LU factorization with partial pivoting, factors stored in u_f (Alg. 4 first
+// line; Gaussian elimination with partial pivoting, Sec. 1), gfx950.
+//
+// Right-looking blocked elimination with panel width nb.  Per panel:
+//
+//  1. k_panel (one workgroup of 1024 threads): the m x nb panel is held in
+//     registers in the arithmetic format (fp32 for u_f in {fp16, bf16, fp32},
+//     fp64 for u_f = fp64), ceil(m/1024) rows per thread.  For each column the
+//     pivot search is a per-thread scan, a 64-lane shuffle butterfly on
+//     (|value|, position) and one LDS exchange between the 16 waves; the wave
+//     that owns the winning row publishes that row in LDS in the same step, so
+//     a column costs a single barrier.  Rows are not moved: each thread keeps
+//     the current position of its rows and the interchange is a relabelling.
+//     Ties go to the lowest position, NaN never wins, a zero pivot column is
+//     recorded in info and left unscaled.  Multipliers use the correctly
+//     rounded reciprocal of the pivot; the rank-1 update uses fused
+//     multiply-adds.  The panel is written back to its final row positions,
+//     rounded to u_f.
+//  2. k_update (one workgroup per 32-column strip): applies the panel's row
+//     interchanges to the strip; for strips right of the panel it solves
+//     U12 = L11^{-1} A12 (forward substitution, fused multiply-adds, rows in
+//     increasing order, rounded to u_f) and subtracts L21 U12 from A22 on the
+//     matrix cores (fp16/bf16 MFMA 32x32x8 with fp32 accumulation; the result
+//     is rounded to u_f), or with fp32/fp64 fused multiply-adds for fp32/fp64
+//     factors.
+#include "common.hpp"
+#include "msir_internal.hpp"
+
+namespace msir {
+
+constexpr int PNT = 1024;         // panel threads
+constexpr int PNW = PNT / 64;     // panel waves
+
+template <int P> struct Arith { typedef float T; };
+template <> struct Arith<P_FP64> { typedef double T; };
+
+__device__ __forceinline__ float a_rcp(float x) { return __fdiv_rn(1.0f, x); }
+__device__ __forceinline__ double a_rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float a_mul(float a, float b) { return __fmul_rn(a, b); }
+__device__ __forceinline__ double a_mul(double a, double b) { return __dmul_rn(a, b); }
+__device__ __forceinline__ float a_fma(float a, float b, float c) { return __fmaf_rn(a, b, c); }
+__device__ __forceinline__ double a_fma(double a, double b, double c) { return __fma_rn(a, b, c); }
+template <int P> __device__ __forceinline__ float to_a(typename Store<P>::T v, float) { return Store<P>::to_f(v); }
+template <int P> __device__ __forceinline__ double to_a(typename Store<P>::T v, double) { return Store<P>::to_d(v); }
+template <int P> __device__ __forceinline__ typename Store<P>::T from_a(float v) { return Store<P>::from_f(v); }
+template <int P> __device__ __forceinline__ typename Store<P>::T from_a(double v) { return Store<P>::from_d(v); }
+
+// ------------------------------------------------------------------ panel
+template <int P, int R, int NB>
+__global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
+                                               int* __restrict__ ipiv, int* __restrict__ info) {
+  typedef typename Arith<P>::T AT;
+  typedef typename Store<P>::T ST;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int m = n - j0;
+  __shared__ AT srow[2][PNW][NB];
+  __shared__ AT sval[2][PNW];
+  __shared__ int spos[2][PNW];
+
+  AT a[R][NB];
+  int pos[R];
+  bool valid[R];
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = tid + s * PNT;
+    valid[s] = r < m;
+    pos[s] = r;
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+      a[s][k] = (valid[s] && k < jb) ? to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + r], AT(0)) : AT(0);
+  }
+
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    if (c < jb) {
+      const int buf = c & 1;
+      // local candidate: largest |a[s][c]| among active rows, lowest position on ties
+      AT bv = AT(-1);
+      int bp = 0x7fffffff;
+      int bs = -1;
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        if (valid[s] && pos[s] >= c) {
+          AT v = fabs(a[s][c]);
+          if (v > bv || (v == bv && pos[s] < bp)) { bv = v; bp = pos[s]; bs = s; }
+        }
+      }
+      AT wvv = bv;
+      int wp = bp;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        AT ov = __shfl_xor(wvv, o, 64);
+        int op = __shfl_xor(wp, o, 64);
+        if (ov > wvv || (ov == wvv && op < wp)) { wvv = ov; wp = op; }
+      }
+      // the owner of the wave's best row publishes it
+      if (bs >= 0 && bp == wp && wvv >= AT(0)) {
+#pragma unroll
+        for (int s = 0; s < R; ++s)
+          if (s == bs) {
+#pragma unroll
+            for (int k = c; k < NB; ++k) srow[buf][wv][k] = a[s][k];
+          }
+      }
+      if (lane == 0) { sval[buf][wv] = wvv; spos[buf][wv] = wp; }
+      __syncthreads();
+      AT gv = sval[buf][0];
+      int gp = spos[buf][0], gw = 0;
+#pragma unroll
+      for (int w = 1; w < PNW; ++w) {
+        AT v = sval[buf][w];
+        int p = spos[buf][w];
+        if (v > gv || (v == gv && p < gp)) { gv = v; gp = p; gw = w; }
+      }
+      if (gv < AT(0)) gp = c;  // no valid candidate (all NaN): no interchange
+      if (tid == 0) {
+        ipiv[j0 + c] = j0 + gp;
+        if (!(gv > AT(0)) && *info == 0) *info = j0 + c + 1;
+      }
+      // interchange = relabelling of positions c and gp
+#pragma unroll
+      for (int s = 0; s < R; ++s) {
+        if (pos[s] == c) pos[s] = gp;
+        else if (pos[s] == gp) pos[s] = c;
+      }
+      if (gv > AT(0)) {
+        const AT piv = srow[buf][gw][c];
+        const AT rcp = a_rcp(piv);
+        AT l[R];
+        bool act[R];
+#pragma unroll
+        for (int s = 0; s < R; ++s) {
+          act[s] = valid[s] && pos[s] > c;
+          l[s] = a_mul(a[s][c], rcp);
+          if (act[s]) a[s][c] = l[s];
+        }
+#pragma unroll
+        for (int k = c + 1; k < NB; ++k) {
+          if (k < jb) {
+            const AT pk = srow[buf][gw][k];
+#pragma unroll
+            for (int s = 0; s < R; ++s)
+              if (act[s]) a[s][k] = a_fma(-l[s], pk, a[s][k]);
+          }
+        }
+      }
+    }
+  }
+  // write the panel back to the final row positions, rounded to u_f
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    if (valid[s]) {
+      const int q = pos[s];
+#pragma unroll
+      for (int k = 0; k < NB; ++k)
+        if (k < jb) W[(size_t)(j0 + k) * ldw + j0 + q] = from_a<P>(a[s][k]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ update
+constexpr int SW = 32;    // strip width
+constexpr int UNT = 256;  // update threads
+
+typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float16_t __attribute__((ext_vector_type(16)));
+
+template <int P>
+__device__ __forceinline__ float16_t mfma_32x32x8(const uint16_t* a4, const uint16_t* b4, float16_t c) {
+  if constexpr (P == P_FP16) {
+    half4_t av, bv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { av[i] = __builtin_bit_cast(_Float16, a4[i]); bv[i] = __builtin_bit_cast(_Float16, b4[i]); }
+    return __builtin_amdgcn_mfma_f32_32x32x8f16(av, bv, c, 0, 0, 0);
+  } else {
+    short4_t av, bv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) { av[i] = (short)a4[i]; bv[i] = (short)b4[i]; }
+    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(av, bv, c, 0, 0, 0);
+  }
+}
+
+template <int P, int KMAX>
+__global__ __launch_bounds__(UNT) void k_update(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
+                                                const int* __restrict__ ipiv) {
+  typedef typename Arith<P>::T AT;
+  typedef typename Store<P>::T ST;
+  const int tid = threadIdx.x;
+  const int c0 = blockIdx.x * SW;
+  const int jr = j0 + jb;  // first trailing column / row
+  __shared__ int spiv[KMAX];
+  __shared__ AT sL[KMAX][KMAX + 1];      // L11 (unit lower), arithmetic format
+  __shared__ ST sU[SW][KMAX + 8];        // U12 (rounded to u_f), [col][k]
+  for (int i = tid; i < jb; i += UNT) spiv[i] = ipiv[j0 + i];
+  const bool has_right = (c0 + SW > jr);
+  if (has_right)
+    for (int e = tid; e < jb * jb; e += UNT) {
+      const int i = e % jb, k = e / jb;
+      sL[i][k] = to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + i], AT(0));
+    }
+  __syncthreads();
+
+  // phase 1: interchanges (all strip columns outside the panel), then U12 for right columns
+  if (tid < SW) {
+    const int col = c0 + tid;
+    const bool in_panel = (col >= j0 && col < jr);
+    if (col < n && !in_panel) {
+      ST* w = W + (size_t)col * ldw;
+      for (int i = 0; i < jb; ++i) {
+        const int p = spiv[i];
+        if (p != j0 + i) {
+          ST t = w[j0 + i];
+          w[j0 + i] = w[p];
+          w[p] = t;
+        }
+      }
+      if (col >= jr) {
+        AT u[KMAX];
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) u[k] = (k < jb) ? to_a<P>(w[j0 + k], AT(0)) : AT(0);
+#pragma unroll
+        for (int k = 1; k < KMAX; ++k) {
+          if (k < jb) {
+            AT acc = u[k];
+#pragma unroll
+            for (int i = 0; i < KMAX; ++i)
+              if (i < k) acc = a_fma(-sL[k][i], u[i], acc);
+            u[k] = acc;
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k)
+          if (k < jb) {
+            const ST sv = from_a<P>(u[k]);
+            w[j0 + k] = sv;
+            sU[tid][k] = sv;
+          }
+      } else {
+#pragma unroll
+        for (int k = 0; k < KMAX; ++k) sU[tid][k] = ST(0);
+      }
+    } else {
+      for (int k = 0; k < KMAX; ++k) sU[tid][k] = ST(0);
+    }
+  }
+  if (!has_right || jr >= n) return;
+  __syncthreads();
+
+  // phase 2: A22 -= L21 U12 on rows [jr, n), strip columns >= jr
+  if constexpr (P == P_FP16 || P == P_BF16) {
+    const int lane = tid & 63, wv = tid >> 6;
+    const int lc = lane & 31;       // column within the strip / row within the tile
+    const int hi = lane >> 5;       // k half / row-group half
+    const int col = c0 + lc;
+    const bool col_ok = (col >= jr) && (col < n);
+    for (int r0 = jr + 32 * wv; r0 < n; r0 += 32 * (UNT / 64)) {
+      float16_t acc;
+      // C tile: lane holds column lc, rows 8g + 4hi + e
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + 8 * g + 4 * hi + e;
+          acc[4 * g + e] = (col < n && r < n) ? Store<P>::to_f(W[(size_t)col * ldw + r]) : 0.0f;
+        }
+      const int ar = r0 + lc;  // A operand row for this lane
+#pragma unroll
+      for (int kk = 0; kk < KMAX; kk += 8) {
+        if (kk < jb) {
+          uint16_t a4[4], b4[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int k = kk + 4 * hi + e;
+            uint16_t av = (ar < n) ? W[(size_t)(j0 + k) * ldw + ar] : (uint16_t)0;
+            a4[e] = av ^ (uint16_t)0x8000;  // -L21 (sign flip is exact)
+            b4[e] = sU[lc][k];
+          }
+          acc = mfma_32x32x8<P>(a4, b4, acc);
+        }
+      }
+      if (col_ok) {
+#pragma unroll
+        for (int g = 0; g < 4; ++g)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int r = r0 + 8 * g + 4 * hi + e;
+            if (r < n) W[(size_t)col * ldw + r] = Store<P>::from_f(acc[4 * g + e]);
+          }
+      }
+    }
+  } else {
+    // fp32 / fp64 factors: one row per thread, SW accumulators
+    for (int r = jr + tid; r < n; r += UNT) {
+      AT acc[SW];
+#pragma unroll
+      for (int q = 0; q < SW; ++q) {
+        const int col = c0 + q;
+        acc[q] = (col >= jr && col < n) ? to_a<P>(W[(size_t)col * ldw + r], AT(0)) : AT(0);
+      }
+      for (int k = 0; k < jb; ++k) {
+        const AT l = to_a<P>(W[(size_t)(j0 + k) * ldw + r], AT(0));
+#pragma unroll
+        for (int q = 0; q < SW; ++q) acc[q] = a_fma(-l, to_a<P>(sU[q][k], AT(0)), acc[q]);
+      }
+#pragma unroll
+      for (int q = 0; q < SW; ++q) {
+        const int col = c0 + q;
+        if (col >= jr && col < n) W[(size_t)col * ldw + r] = from_a<P>(acc[q]);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------ driver
+template <int P, int R, int NB>
+static void launch_panel(Ctx& c, void* W, int ldw, int n, int j0, int jb, int* ipiv, int* info) {
+  k_panel<P, R, NB><<<1, PNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, ipiv, info);
+}
+
+template <int P, int NB>
+static void panel_dispatch(Ctx& c, void* W, int ldw, int n, int j0, int jb, int* ipiv, int* info) {
+  const int m = n - j0;
+  const int R = (m + PNT - 1) / PNT;
+  constexpr int CAP = (P == P_FP64) ? 32 : 64;  // register values per thread
+  if (R <= 1) launch_panel<P, 1, NB>(c, W, ldw, n, j0, jb, ipiv, info);
+  else if (R <= 2 && 2 * NB <= CAP) launch_panel<P, (2 * NB <= CAP ? 2 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info);
+  else if (R <= 4 && 4 * NB <= CAP) launch_panel<P, (4 * NB <= CAP ? 4 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info);
+  else launch_panel<P, (8 * NB <= CAP ? 8 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info);
+}
+
+template <int P, int NB>
+static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info) {
+  const int nstrips = (n + SW - 1) / SW;
+  for (int j0 = 0; j0 < n; j0 += NB) {
+    const int jb = (n - j0 < NB) ? n - j0 : NB;
+    panel_dispatch<P, NB>(c, W, ldw, n, j0, jb, ipiv, info);
+    if (nstrips > 1 || n > jb)
+      k_update<P, NB><<<nstrips, UNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, ipiv);
+  }
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+int nb_auto(int n, int prec) {
+  const int R = (n + PNT - 1) / PNT;
+  int nb = R <= 1 ? 64 : R <= 2 ? 32 : R <= 4 ? 16 : 8;
+  if (prec == P_FP64) nb /= 2;
+  return nb;
+}
+
+bool nb_ok(int n, int prec, int nb) {
+  const int R = (n + PNT - 1) / PNT;
+  const int cap = (prec == P_FP64) ? 32 : 64;
+  int Rp = R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : 8;
+  if (R > 8) return false;
+  if (!(nb == 4 || nb == 8 || nb == 16 || nb == 32 || nb == 64)) return false;
+  if (prec == P_FP64 && nb == 64) return false;
+  if (prec != P_FP64 && nb == 4) return false;
+  return Rp * nb <= cap;
+}
+
+template <int P>
+static int getrf_p(Ctx& c, int n, void* W, int ldw, int nb, int* ipiv, int* info) {
+  if constexpr (P == P_FP64) {
+    switch (nb) {
+      case 4: return getrf_nb<P, 4>(c, n, W, ldw, ipiv, info);
+      case 8: return getrf_nb<P, 8>(c, n, W, ldw, ipiv, info);
+      case 16: return getrf_nb<P, 16>(c, n, W, ldw, ipiv, info);
+      case 32: return getrf_nb<P, 32>(c, n, W, ldw, ipiv, info);
+    }
+  } else {
+    switch (nb) {
+      case 8: return getrf_nb<P, 8>(c, n, W, ldw, ipiv, info);
+      case 16: return getrf_nb<P, 16>(c, n, W, ldw, ipiv, info);
+      case 32: return getrf_nb<P, 32>(c, n, W, ldw, ipiv, info);
+      case 64: return getrf_nb<P, 64>(c, n, W, ldw, ipiv, info);
+    }
+  }
+  return -6;
+}
+
+int getrf(Ctx& c, int n, int prec, void* W, int ldw, int nb, int* ipiv, int* info_dev) {
+  if (nb == 0) nb = nb_auto(n, prec);
+  if (!nb_ok(n, prec, nb)) return -6;
+  HIP_CHECK(hipMemsetAsync(info_dev, 0, sizeof(int), c.stream));
+  switch (prec) {
+    case P_FP16: return getrf_p<P_FP16>(c, n, W, ldw, nb, ipiv, info_dev);
+    case P_BF16: return getrf_p<P_BF16>(c, n, W, ldw, nb, ipiv, info_dev);
+    case P_FP32: return getrf_p<P_FP32>(c, n, W, ldw, nb, ipiv, info_dev);
+    case P_FP64: return getrf_p<P_FP64>(c, n, W, ldw, nb, ipiv, info_dev);
+  }
+  return -3;
+}
+
+}  // namespace msir

@@ -1,0 +1,221 @@
+// Left-preconditioned GMRES for the correction equation (Alg. 2 GMRES-IR and
+// Alg. 3 SGMRES-IR), gfx950.
+//
+// Per iteration: w = fl_u(M^{-1} (A v_j)) with A v_j and the triangular solves
+// in the operator precision p (matvec + trsv launches), then k_arnoldi: one
+// workgroup of 1024 threads holds w in registers and runs modified
+// Gram-Schmidt against v_0..v_j (float64 inner products, each update
+// w <- fl_u(w - h v_i) with separately rounded multiply and subtract), the
+// norm, the Givens rotation update of the Hessenberg column and of the
+// residual vector g in float64, and the stopping test |g_{j+1}| <= tau beta0.
+// A device status word (done, iterations) makes every later launch of the
+// same cycle a no-op, so the host only synchronises every few iterations.
+// After a cycle: y = R^{-1} g by one wave, delta = fl_u(V y), d += delta; with a
+// restart length the preconditioned residual is updated as
+// fl_u(c - fl_u(M^{-1} A delta)).
+#include "common.hpp"
+#include "msir_internal.hpp"
+#include "gmres.hpp"
+
+namespace msir {
+
+constexpr int GNT = 1024;
+constexpr int GPT = MSIR_MAX_N / GNT;  // values per thread
+
+// beta = ||resid||_2; g[0] = beta; V0 = fl_u(resid / beta); status reset
+__global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __restrict__ resid, double* __restrict__ V0,
+                                                     double* __restrict__ g, double* __restrict__ beta0, int first,
+                                                     int u, GStatus* st) {
+  __shared__ double sh[GNT / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += GNT) acc = __fma_rn(resid[i], resid[i], acc);
+  const double beta = sqrt(block_sum<GNT>(acc, sh));
+  for (int i = threadIdx.x; i < n; i += GNT) V0[i] = round_to(resid[i] / beta, u);
+  if (threadIdx.x == 0) {
+    g[0] = beta;
+    if (first) *beta0 = beta;
+    st->jcount = 0;
+    const bool bad = !__builtin_isfinite(beta);
+    st->done = (beta == 0.0 || bad) ? 1 : 0;
+    if (first) st->nan = bad ? 1 : 0;
+  }
+}
+
+__global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restrict__ V, int ldv,
+                                                 const double* __restrict__ w_in, double* __restrict__ H, int ldh,
+                                                 double* __restrict__ cs, double* __restrict__ sn,
+                                                 double* __restrict__ g, const double* __restrict__ beta0, double tau,
+                                                 int u, GStatus* st) {
+  if (st->done) return;
+  __shared__ double sh[GNT / 64];
+  __shared__ double s_hn;
+  const int tid = threadIdx.x;
+  double w[GPT];
+#pragma unroll
+  for (int t = 0; t < GPT; ++t) {
+    const int i = tid + t * GNT;
+    w[t] = i < n ? w_in[i] : 0.0;
+  }
+  for (int i = 0; i <= j; ++i) {
+    const double* v = V + (size_t)i * ldv;
+    double acc = 0.0;
+#pragma unroll
+    for (int t = 0; t < GPT; ++t) {
+      const int r = tid + t * GNT;
+      if (r < n) acc = __fma_rn(v[r], w[t], acc);
+    }
+    const double h = block_sum<GNT>(acc, sh);
+#pragma unroll
+    for (int t = 0; t < GPT; ++t) {
+      const int r = tid + t * GNT;
+      if (r < n) w[t] = round_to(__dsub_rn(w[t], __dmul_rn(h, v[r])), u);
+    }
+    if (tid == 0) H[(size_t)j * ldh + i] = h;
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < GPT; ++t) acc = __fma_rn(w[t], w[t], acc);
+  const double hn = sqrt(block_sum<GNT>(acc, sh));
+  if (tid == 0) {
+    double* hc = H + (size_t)j * ldh;
+    hc[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+      const double a = hc[i], b = hc[i + 1];
+      hc[i] = __dadd_rn(__dmul_rn(cs[i], a), __dmul_rn(sn[i], b));
+      hc[i + 1] = __dadd_rn(__dmul_rn(-sn[i], a), __dmul_rn(cs[i], b));
+    }
+    const double a = hc[j], b = hc[j + 1];
+    const double r = hypot(a, b);
+    double c = 1.0, s = 0.0;
+    if (r != 0.0) { c = a / r; s = b / r; }
+    cs[j] = c; sn[j] = s;
+    hc[j] = r;
+    hc[j + 1] = 0.0;
+    const double gj = g[j];
+    g[j + 1] = __dmul_rn(-s, gj);
+    g[j] = __dmul_rn(c, gj);
+    const double e = fabs(g[j + 1]);
+    const bool stop = !__builtin_isfinite(g[j + 1]) || e <= tau * (*beta0) || hn == 0.0;
+    st->jcount = j + 1;
+    st->done = stop ? 1 : 0;
+    s_hn = hn;
+  }
+  __syncthreads();
+  const double hh = s_hn;
+  double* vn = V + (size_t)(j + 1) * ldv;
+#pragma unroll
+  for (int t = 0; t < GPT; ++t) {
+    const int r = tid + t * GNT;
+    if (r < n) vn[r] = round_to(w[t] / hh, u);
+  }
+}
+
+// y = R^{-1} g (upper triangular from the rotated Hessenberg), one wave,
+// column-oriented back substitution with g held in LDS.
+constexpr int LSQ_MAX = 8192;
+__global__ __launch_bounds__(64) void k_lsq(const double* __restrict__ H, int ldh, const double* __restrict__ g,
+                                            double* __restrict__ y, const GStatus* st) {
+  __shared__ double sg[LSQ_MAX];
+  const int j = st->jcount;
+  const int l = threadIdx.x;
+  for (int i = l; i < j; i += 64) sg[i] = g[i];
+  __builtin_amdgcn_wave_barrier();
+  for (int i = j - 1; i >= 0; --i) {
+    const double yi = sg[i] / H[(size_t)i * ldh + i];
+    if (l == 0) y[i] = yi;
+    for (int k = l; k < i; k += 64) sg[k] = __dsub_rn(sg[k], __dmul_rn(H[(size_t)i * ldh + k], yi));
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// delta = fl_u(V[:, :j] y); d_acc += delta
+__global__ __launch_bounds__(256) void k_combine(int n, const double* __restrict__ V, int ldv,
+                                                 const double* __restrict__ y, const GStatus* st, int u,
+                                                 double* __restrict__ delta, double* __restrict__ dacc) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  const int j = st->jcount;
+  double acc = 0.0;
+  for (int i = 0; i < j; ++i) acc = __fma_rn(V[(size_t)i * ldv + r], y[i], acc);
+  const double dl = round_to(acc, u);
+  delta[r] = dl;
+  dacc[r] = __dadd_rn(dacc[r], dl);
+}
+
+// resid = fl_u(resid - w)
+__global__ __launch_bounds__(256) void k_resid_update(int n, double* __restrict__ resid, const double* __restrict__ w,
+                                                      int u) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  resid[r] = round_to(__dsub_rn(resid[r], w[r]), u);
+}
+
+// d = fl_u(d_acc), NaN when the first preconditioned residual was not finite
+__global__ __launch_bounds__(256) void k_finish(int n, const double* __restrict__ dacc, const GStatus* st, int u,
+                                                double* __restrict__ d) {
+  const int r = blockIdx.x * 256 + threadIdx.x;
+  if (r >= n) return;
+  d[r] = st->nan ? __builtin_nan("") : round_to(dacc[r], u);
+}
+
+int gmres(Ctx& c, GmresWork& gw, const GmresOp& op, const double* rhat, double tau, double k_max, int restart,
+          double* d, int* k_out) {
+  const int n = op.n;
+  int k_cap = (int)ceil(k_max);
+  if (k_cap > op.n) k_cap = op.n;
+  if (k_cap < 1) k_cap = 1;
+  const int u = op.u;
+  const int p = op.p;
+  const int nb256 = (n + 255) / 256;
+  int rc = gw.ensure(c, n, restart > 0 ? (restart < k_cap ? restart : k_cap) : k_cap);
+  if (rc) return rc;
+  GStatus* st = gw.status;
+  HIP_CHECK(hipMemsetAsync(gw.dacc, 0, n * sizeof(double), c.stream));
+  HIP_CHECK(hipMemsetAsync(st, 0, sizeof(GStatus), c.stream));
+  // c0 = fl_u(M^{-1} rhat)
+  rc = op.apply_solve(c, rhat, nullptr, gw.resid, nullptr);
+  if (rc) return rc;
+  int k = 0;
+  bool first = true;
+  const int ldv = n;
+  const int ldh = gw.mcap + 1;
+  for (;;) {
+    int m = restart > 0 ? restart : k_cap;
+    if (m > k_cap - k) m = k_cap - k;
+    k_gmres_start<<<1, GNT, 0, c.stream>>>(n, gw.resid, gw.V, gw.g, gw.beta0, first ? 1 : 0, u, st);
+    HIP_CHECK(hipGetLastError());
+    first = false;
+    int jdone = 0;
+    const int CHK = 8;
+    for (int it = 0; it < m; ++it) {
+      rc = op.apply_full(c, gw.V + (size_t)it * ldv, gw.w, &st->done);
+      if (rc) return rc;
+      k_arnoldi<<<1, GNT, 0, c.stream>>>(n, it, gw.V, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g, gw.beta0, tau, u, st);
+      HIP_CHECK(hipGetLastError());
+      if ((it + 1) % CHK == 0 || it + 1 == m) {
+        HIP_CHECK(hipMemcpyAsync(gw.host_status, st, sizeof(GStatus), hipMemcpyDeviceToHost, c.stream));
+        HIP_CHECK(hipStreamSynchronize(c.stream));
+        if (gw.host_status->done) break;
+      }
+    }
+    HIP_CHECK(hipMemcpyAsync(gw.host_status, st, sizeof(GStatus), hipMemcpyDeviceToHost, c.stream));
+    HIP_CHECK(hipStreamSynchronize(c.stream));
+    jdone = gw.host_status->jcount;
+    const bool stop = gw.host_status->done != 0;
+    k_lsq<<<1, 64, 0, c.stream>>>(gw.H, ldh, gw.g, gw.y, st);
+    k_combine<<<nb256, 256, 0, c.stream>>>(n, gw.V, ldv, gw.y, st, u, gw.delta, gw.dacc);
+    HIP_CHECK(hipGetLastError());
+    k += jdone;
+    if (stop || k >= k_cap || jdone == 0) break;
+    rc = op.apply_full(c, gw.delta, gw.w, nullptr);
+    if (rc) return rc;
+    k_resid_update<<<nb256, 256, 0, c.stream>>>(n, gw.resid, gw.w, u);
+    HIP_CHECK(hipGetLastError());
+  }
+  k_finish<<<nb256, 256, 0, c.stream>>>(n, gw.dacc, st, u, d);
+  HIP_CHECK(hipGetLastError());
+  *k_out = k;
+  return 0;
+}
+
+}  // namespace msir

@@ -1,0 +1,943 @@
+// Host side of libmsir: handle and workspace, the multistage controller of
+// Alg. 4 (stopping criteria of Sec. 2.1.1, scalings of Sec. 2.1.2), and the
+// C ABI declared in include/msir.h.
+//
+// The controller runs on the host and reads a few scalars per refinement step
+// (||r||_inf, ||d||_inf, ||x||_inf and a non-finite flag) from pinned memory;
+// everything of size n or n^2 stays on the device.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "../../include/msir.h"
+#include "common.hpp"
+#include "gmres.hpp"
+#include "msir_internal.hpp"
+
+static thread_local char g_err[512];
+
+void msir_set_error(const char* what, const char* file, int line) {
+  snprintf(g_err, sizeof(g_err), "%s (%s:%d)", what, file, line);
+}
+
+namespace msir {
+
+// ------------------------------------------------------------------ context
+int Ctx::alloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 8;
+  if (budget && used + bytes > budget) return MSIR_ERR_ALLOC;
+  if (hipMalloc(p, bytes) != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return MSIR_ERR_ALLOC;
+  }
+  used += bytes;
+  return 0;
+}
+
+void Ctx::release(void* p, size_t bytes) {
+  if (p) {
+    (void)hipFree(p);
+    used -= std::min(used, bytes);
+  }
+}
+
+void* Ctx::grow(DevBuf& b, size_t bytes) {
+  if (b.bytes >= bytes && b.p) return b.p;
+  if (b.p) {
+    (void)hipStreamSynchronize(stream);
+    release(b.p, b.bytes);
+    b.p = nullptr;
+    b.bytes = 0;
+  }
+  size_t want = std::max(bytes, (size_t)4096);
+  void* p = nullptr;
+  if (alloc(&p, want)) return nullptr;
+  (void)hipMemsetAsync(p, 0, want, stream);
+  b.p = p;
+  b.bytes = want;
+  return p;
+}
+
+// ------------------------------------------------------------------ GMRES workspace
+int GmresWork::ensure(Ctx& c, int n, int m) {
+  if (n <= ncap && m <= mcap && V) return 0;
+  if (buf.p) {
+    (void)hipStreamSynchronize(c.stream);
+    c.release(buf.p, buf.bytes);
+    buf.p = nullptr;
+    buf.bytes = 0;
+  }
+  ncap = std::max(n, ncap);
+  mcap = std::max(m, mcap);
+  const size_t nv = (size_t)(mcap + 1) * ncap;
+  const size_t nh = (size_t)(mcap + 1) * (mcap + 1);
+  const size_t total = nv + nh + 4 * (size_t)(mcap + 2) + 4 * (size_t)ncap + 8 + 8;
+  void* p = nullptr;
+  if (c.alloc(&p, total * sizeof(double))) return MSIR_ERR_ALLOC;
+  buf.p = p;
+  buf.bytes = total * sizeof(double);
+  double* q = (double*)p;
+  V = q; q += nv;
+  H = q; q += nh;
+  cs = q; q += mcap + 2;
+  sn = q; q += mcap + 2;
+  g = q; q += mcap + 2;
+  y = q; q += mcap + 2;
+  w = q; q += ncap;
+  resid = q; q += ncap;
+  delta = q; q += ncap;
+  dacc = q; q += ncap;
+  beta0 = q; q += 8;
+  status = (GStatus*)q;
+  if (!host_status) {
+    if (hipHostMalloc((void**)&host_status, sizeof(GStatus)) != hipSuccess) return MSIR_ERR_HIP;
+  }
+  return 0;
+}
+
+void GmresWork::free_all(Ctx& c) {
+  if (buf.p) c.release(buf.p, buf.bytes);
+  buf.p = nullptr;
+  buf.bytes = 0;
+  if (host_status) (void)hipHostFree(host_status);
+  host_status = nullptr;
+  V = nullptr;
+  ncap = mcap = 0;
+}
+
+int GmresOp::apply_solve(Ctx& c, const double* t, const int* skip, double* out, const int*) const {
+  TrsvArgs a;
+  a.n = n; a.prec = prec; a.W = W; a.ldw = ldw; a.perm = perm; a.rinv = rinv; a.R = R; a.S = S; a.mu = mu;
+  a.comp = p; a.mode = mode; a.t_hi = t; a.t_lo = nullptr; a.y_hi = out; a.y_lo = nullptr; a.out_round = u;
+  a.skip = skip; a.dinv = dinv;
+  return trsv(c, a);
+}
+
+int GmresOp::apply_full(Ctx& c, const double* v, double* out, const int* skip) const {
+  int rc = matvec(c, n, A, lda, Au, n, v, p, tmp_hi, tmp_lo, skip);
+  if (rc) return rc;
+  TrsvArgs a;
+  a.n = n; a.prec = prec; a.W = W; a.ldw = ldw; a.perm = perm; a.rinv = rinv; a.R = R; a.S = S; a.mu = mu;
+  a.comp = p; a.mode = mode; a.t_hi = tmp_hi; a.t_lo = (p == P_DD) ? tmp_lo : nullptr; a.y_hi = out;
+  a.y_lo = nullptr; a.out_round = u; a.skip = skip; a.dinv = dinv;
+  return trsv(c, a);
+}
+
+// ------------------------------------------------------------------ formats
+static double unit_roundoff(int p) {
+  switch (p) {
+    case P_FP16: return ldexp(1.0, -11);
+    case P_BF16: return ldexp(1.0, -8);
+    case P_FP32: return ldexp(1.0, -24);
+    case P_FP64: return ldexp(1.0, -53);
+    default: return ldexp(1.0, -106);
+  }
+}
+static size_t store_bytes(int p) { return p == P_FP64 ? 8 : p == P_FP32 ? 4 : 2; }
+static int square_of(int u) { return u == P_FP32 ? P_FP64 : P_DD; }
+static int next_uf(int uf) {
+  const double target = unit_roundoff(uf) * unit_roundoff(uf);
+  const int order[4] = {P_FP16, P_BF16, P_FP32, P_FP64};
+  for (int f : order)
+    if (unit_roundoff(f) <= target) return f;
+  return -1;
+}
+
+}  // namespace msir
+
+using namespace msir;
+
+// ------------------------------------------------------------------ handle
+struct FactorState {
+  int prec = -1;
+  int n = 0;
+  void* W = nullptr;
+  size_t Wbytes = 0;
+  int* ipiv = nullptr;
+  int* perm = nullptr;
+  double* rinv = nullptr;
+  double* R = nullptr;
+  double* S = nullptr;
+  double* mu_dev = nullptr;
+  double mu = 1.0;
+  bool scaled = false;
+  int info = 0;
+  size_t vec_bytes = 0;
+};
+
+struct msir_handle {
+  Ctx c;
+  GmresWork gw;
+  FactorState f;
+  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, dinv;
+  double* dev_small = nullptr;   // device scalars
+  double* host_small = nullptr;  // pinned host scalars
+  std::vector<int> hpiv, hperm;
+  hipEvent_t ev[4];
+};
+
+static int ensure_factor(msir_handle* h, int n, int prec) {
+  FactorState& f = h->f;
+  const size_t wb = (size_t)n * n * store_bytes(prec);
+  if (f.Wbytes < wb) {
+    if (f.W) { (void)hipStreamSynchronize(h->c.stream); h->c.release(f.W, f.Wbytes); f.W = nullptr; f.Wbytes = 0; }
+    if (h->c.alloc(&f.W, wb)) return MSIR_ERR_ALLOC;
+    f.Wbytes = wb;
+  }
+  const size_t vb = (size_t)n * (2 * sizeof(int) + 3 * sizeof(double)) + 64;
+  if (f.vec_bytes < vb) {
+    if (f.rinv) { (void)hipStreamSynchronize(h->c.stream); h->c.release(f.rinv, f.vec_bytes); f.rinv = nullptr; }
+    void* p = nullptr;
+    if (h->c.alloc(&p, vb)) return MSIR_ERR_ALLOC;
+    f.vec_bytes = vb;
+    char* q = (char*)p;                       // [rinv | R | S | ipiv | perm]
+    f.rinv = (double*)q; q += n * sizeof(double);
+    f.R = (double*)q; q += n * sizeof(double);
+    f.S = (double*)q; q += n * sizeof(double);
+    f.ipiv = (int*)q; q += n * sizeof(int);
+    f.perm = (int*)q;
+  }
+  f.prec = prec;
+  f.n = n;
+  return 0;
+}
+
+static double* vbuf(msir_handle* h, DevBuf& b, size_t n) { return (double*)h->c.grow(b, n * sizeof(double)); }
+
+static int sync_read(msir_handle* h, const double* dev, int count) {
+  HIP_CHECK(hipMemcpyAsync(h->host_small, dev, count * sizeof(double), hipMemcpyDeviceToHost, h->c.stream));
+  HIP_CHECK(hipStreamSynchronize(h->c.stream));
+  return 0;
+}
+
+// Factor A in u_f = prec with the Sec. 2.1.2 policy.  Leaves factors in h->f.
+static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, int scaling_mode, int nb) {
+  int rc = ensure_factor(h, n, prec);
+  if (rc) return rc;
+  FactorState& f = h->f;
+  Ctx& c = h->c;
+  double* dmu = h->dev_small + 8;
+  double* dtmp = vbuf(h, h->tmp_lo, n);
+  if (!dtmp) return MSIR_ERR_ALLOC;
+  const bool fp16 = prec == P_FP16;
+  bool use_scaling = fp16 && (scaling_mode == MSIR_SCALE_ALWAYS || scaling_mode == MSIR_SCALE_COLS);
+  f.scaled = false;
+  f.mu = 1.0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    if (use_scaling) {
+      const int rows = (scaling_mode == MSIR_SCALE_COLS) ? 0 : 1;
+      rc = scaling(c, n, A, lda, prec, rows, f.R, f.S, dmu, dtmp);
+      if (rc) return rc;
+      rc = sync_read(h, dmu, 1);
+      if (rc) return rc;
+      f.mu = h->host_small[0];
+      f.scaled = true;
+      rc = convert(c, n, A, lda, prec, f.R, f.S, f.mu, f.W, n);
+    } else {
+      rc = convert(c, n, A, lda, prec, nullptr, nullptr, 1.0, f.W, n);
+    }
+    if (rc) return rc;
+    int* dinfo = (int*)(h->dev_small + 16);
+    rc = getrf(c, n, prec, f.W, n, nb, f.ipiv, dinfo);
+    if (rc) return rc;
+    if (fp16 && scaling_mode == MSIR_SCALE_AUTO && !use_scaling) {
+      rc = factors_finite(c, n, prec, f.W, n, h->dev_small + 20);
+      if (rc) return rc;
+      rc = sync_read(h, h->dev_small + 20, 1);
+      if (rc) return rc;
+      if (h->host_small[0] != 0.0) {
+        use_scaling = true;   // retry with two-sided scaling (scaling_mode AUTO -> rows)
+        continue;
+      }
+    }
+    break;
+  }
+  // interchanges -> permutation (host), reciprocals of U's diagonal
+  h->hpiv.resize(n);
+  h->hperm.resize(n);
+  HIP_CHECK(hipMemcpyAsync(h->hpiv.data(), f.ipiv, n * sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  HIP_CHECK(hipMemcpyAsync(h->host_small, h->dev_small + 16, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  HIP_CHECK(hipStreamSynchronize(c.stream));
+  memcpy(&f.info, h->host_small, sizeof(int));
+  for (int i = 0; i < n; ++i) h->hperm[i] = i;
+  for (int j = 0; j < n; ++j) {
+    const int k = h->hpiv[j];
+    if (k != j) std::swap(h->hperm[j], h->hperm[k]);
+  }
+  HIP_CHECK(hipMemcpyAsync(f.perm, h->hperm.data(), n * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  rc = diag_reciprocals(c, n, prec, f.W, n, f.rinv);
+  if (rc) return rc;
+  HIP_CHECK(hipStreamSynchronize(c.stream));
+  return 0;
+}
+
+// Solve with the factors in h->f: y = round_out(M^{-1} t) with components in comp.
+static int solve_with(msir_handle* h, int n, int comp, const double* t_hi, const double* t_lo, double* y,
+                      int out_round, int mode) {
+  FactorState& f = h->f;
+  TrsvArgs a;
+  a.n = n; a.prec = f.prec; a.W = f.W; a.ldw = n; a.perm = f.perm; a.rinv = f.rinv;
+  a.R = f.scaled ? f.R : nullptr; a.S = f.scaled ? f.S : nullptr; a.mu = f.scaled ? f.mu : 1.0;
+  a.comp = comp; a.mode = mode; a.t_hi = t_hi; a.t_lo = t_lo; a.y_hi = y; a.y_lo = nullptr;
+  a.out_round = out_round; a.skip = nullptr; a.dinv = nullptr;
+  return trsv(h->c, a);
+}
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* msir_status_string(int s) {
+  switch (s) {
+    case MSIR_OK: return "converged";
+    case MSIR_NOT_CONVERGED: return "not converged (precision ladder exhausted or step cap reached)";
+    case MSIR_SINGULAR: return "singular factor at the highest precision";
+    case MSIR_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
+    case MSIR_ERR_ALLOC: return "device memory could not be allocated within the handle budget";
+    case MSIR_ERR_SIZE: return "n outside [1, 8192]";
+  }
+  if (s < 0) return "invalid argument";
+  return "unknown status";
+}
+
+void msir_params_default(msir_params* p) {
+  if (!p) return;
+  p->uf = MSIR_FP16;
+  p->u = MSIR_FP32;
+  p->ur = MSIR_FP64;
+  p->ux = MSIR_FP64;
+  p->i_max = 10;
+  p->tau = 0.0;
+  p->rho_thresh = 0.5;
+  p->k_max = 0.0;
+  p->restart = 0;
+  p->conv = MSIR_CONV_BACKWARD;
+  p->tol_nbe = 1e-15;
+  p->scaling = MSIR_SCALE_AUTO;
+  p->nb = 0;
+  p->max_steps = 1000;
+}
+
+int msir_nb_auto(int n, msir_prec fmt) { return nb_auto(n, (int)fmt); }
+
+int msir_create(msir_handle** hp, int device, size_t budget, void* stream) {
+  if (!hp) return -1;
+  *hp = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return -2;
+  HIP_CHECK(hipSetDevice(device));
+  msir_handle* h = new msir_handle();
+  h->c.device = device;
+  h->c.stream = (hipStream_t)stream;
+  h->c.budget = budget;
+  void* p = nullptr;
+  if (h->c.alloc(&p, 4096)) { delete h; return MSIR_ERR_ALLOC; }
+  HIP_CHECK(hipMemset(p, 0, 4096));
+  h->c.counter = (unsigned*)p;
+  h->c.tickets = (unsigned long long*)((char*)p + 64);
+  h->dev_small = (double*)((char*)p + 1024);
+  h->c.scalars = h->dev_small;
+  {
+    const double minus1 = -1.0;
+    HIP_CHECK(hipMemcpy(h->dev_small + 60, &minus1, sizeof(double), hipMemcpyHostToDevice));
+  }
+  if (h->c.alloc((void**)&h->c.blockmax, Ctx::kMaxBlocks * sizeof(double) * 2)) { delete h; return MSIR_ERR_ALLOC; }
+  HIP_CHECK(hipHostMalloc((void**)&h->host_small, 64 * sizeof(double)));
+  for (int i = 0; i < 4; ++i) HIP_CHECK(hipEventCreate(&h->ev[i]));
+  *hp = h;
+  return 0;
+}
+
+int msir_destroy(msir_handle* h) {
+  if (!h) return 0;
+  (void)hipSetDevice(h->c.device);
+  (void)hipStreamSynchronize(h->c.stream);
+  Ctx& c = h->c;
+  DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
+                    &c.tmp_scalar, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
+                    &h->dinv};
+  for (DevBuf* b : bufs) c.release(b->p, b->bytes);
+  if (h->f.W) c.release(h->f.W, h->f.Wbytes);
+  if (h->f.rinv) c.release(h->f.rinv, h->f.vec_bytes);
+  h->gw.free_all(c);
+  c.release(c.blockmax, 0);
+  c.release(c.counter, 0);
+  if (h->host_small) (void)hipHostFree(h->host_small);
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(h->ev[i]);
+  delete h;
+  return 0;
+}
+
+size_t msir_workspace_bytes(int n, const msir_params* pp) {
+  msir_params p;
+  if (pp) p = *pp; else msir_params_default(&p);
+  const double km = p.k_max > 0 ? p.k_max : 0.1 * n;
+  int kc = (int)ceil(km);
+  int m = p.restart > 0 ? std::min(p.restart, kc) : kc;
+  size_t b = (size_t)n * n * 8;                        // factors up to fp64
+  if (p.u == MSIR_FP32) b += (size_t)n * n * 4;        // fp32 copy of A
+  b += (size_t)(m + 1) * n * 8 + (size_t)(m + 1) * (m + 1) * 8;
+  b += (size_t)n * 8 * 40 + (1 << 20);
+  return b;
+}
+
+int msir_convert(msir_handle* h, int n, const double* dA, int lda, msir_prec f, const double* R, const double* S,
+                 double mu, void* dW, int ldw) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (!dA) return -3;
+  if (lda < n) return -4;
+  if (f < MSIR_FP16 || f > MSIR_FP64) return -5;
+  if (!dW) return -9;
+  if (ldw < n) return -10;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  double *dR = nullptr, *dS = nullptr;
+  if (R || S) {
+    if (!R || !S) return -6;
+    dR = vbuf(h, h->tmp_hi, 2 * (size_t)n);
+    if (!dR) return MSIR_ERR_ALLOC;
+    dS = dR + n;
+    HIP_CHECK(hipMemcpyAsync(dR, R, n * sizeof(double), hipMemcpyHostToDevice, h->c.stream));
+    HIP_CHECK(hipMemcpyAsync(dS, S, n * sizeof(double), hipMemcpyHostToDevice, h->c.stream));
+  }
+  int rc = convert(h->c, n, dA, lda, f, dR, dS, mu, dW, ldw);
+  if (rc) return rc;
+  HIP_CHECK(hipStreamSynchronize(h->c.stream));
+  return 0;
+}
+
+int msir_scaling(msir_handle* h, int n, const double* dA, int lda, msir_prec f, int rows, double* R, double* S,
+                 double* mu) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (!dA) return -3;
+  if (lda < n) return -4;
+  if (!R || !S || !mu) return -7;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  double* d = vbuf(h, h->tmp_hi, 3 * (size_t)n + 8);
+  if (!d) return MSIR_ERR_ALLOC;
+  double* dtmp = vbuf(h, h->tmp_lo, n);
+  if (!dtmp) return MSIR_ERR_ALLOC;
+  int rc = scaling(h->c, n, dA, lda, f, rows, d, d + n, d + 2 * n, dtmp);
+  if (rc) return rc;
+  HIP_CHECK(hipMemcpyAsync(R, d, n * sizeof(double), hipMemcpyDeviceToHost, h->c.stream));
+  HIP_CHECK(hipMemcpyAsync(S, d + n, n * sizeof(double), hipMemcpyDeviceToHost, h->c.stream));
+  HIP_CHECK(hipMemcpyAsync(mu, d + 2 * n, sizeof(double), hipMemcpyDeviceToHost, h->c.stream));
+  HIP_CHECK(hipStreamSynchronize(h->c.stream));
+  return 0;
+}
+
+int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, int nb, int* dipiv, int* info) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (f < MSIR_FP16 || f > MSIR_FP64) return -3;
+  if (!dW) return -4;
+  if (ldw < n) return -5;
+  if (nb != 0 && !nb_ok(n, f, nb)) return -6;
+  if (!dipiv) return -7;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  int* dinfo = (int*)(h->dev_small + 16);
+  int rc = getrf(h->c, n, f, dW, ldw, nb, dipiv, dinfo);
+  if (rc) return rc;
+  int hinfo = 0;
+  HIP_CHECK(hipMemcpyAsync(h->host_small, dinfo, sizeof(int), hipMemcpyDeviceToHost, h->c.stream));
+  HIP_CHECK(hipStreamSynchronize(h->c.stream));
+  memcpy(&hinfo, h->host_small, sizeof(int));
+  if (info) *info = hinfo;
+  return 0;
+}
+
+int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, const int* dipiv, const double* dR,
+               const double* dS, double mu, msir_prec comp, int mode, const double* dt, double* dy) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (f < MSIR_FP16 || f > MSIR_FP64) return -3;
+  if (!dW) return -4;
+  if (ldw < n) return -5;
+  if (!dipiv) return -6;
+  if (comp < MSIR_FP16 || comp > MSIR_DD) return -10;
+  if (mode != 0) return -11;
+  if (!dt) return -12;
+  if (!dy) return -13;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  // interchanges -> permutation
+  std::vector<int> piv(n), perm(n);
+  HIP_CHECK(hipMemcpy(piv.data(), dipiv, n * sizeof(int), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  for (int j = 0; j < n; ++j)
+    if (piv[j] != j) std::swap(perm[j], perm[piv[j]]);
+  int* dperm = (int*)vbuf(h, h->tmp_lo, n);
+  double* rinv = vbuf(h, h->d, n);
+  if (!dperm || !rinv) return MSIR_ERR_ALLOC;
+  HIP_CHECK(hipMemcpyAsync(dperm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
+  int rc = diag_reciprocals(h->c, n, f, dW, ldw, rinv);
+  if (rc) return rc;
+  TrsvArgs a;
+  a.n = n; a.prec = f; a.W = dW; a.ldw = ldw; a.perm = dperm; a.rinv = rinv; a.R = dR; a.S = dS;
+  a.mu = (dR || dS) ? mu : 1.0;
+  if ((dR == nullptr) != (dS == nullptr)) return -7;
+  a.comp = comp; a.mode = mode; a.t_hi = dt; a.t_lo = (comp == MSIR_DD) ? dt + n : nullptr;
+  a.y_hi = dy; a.y_lo = (comp == MSIR_DD) ? dy + n : nullptr; a.out_round = -1; a.skip = nullptr; a.dinv = nullptr;
+  rc = trsv(h->c, a);
+  if (rc) return rc;
+  HIP_CHECK(hipStreamSynchronize(h->c.stream));
+  return 0;
+}
+
+int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double* dx, const double* db,
+                  msir_prec ur, msir_prec u, double* drhat, double* s) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (!dA) return -3;
+  if (lda < n) return -4;
+  if (!dx) return -5;
+  if (!db) return -6;
+  if (ur != MSIR_FP64 && ur != MSIR_DD) return -7;
+  if (u < MSIR_FP16 || u > MSIR_FP64) return -8;
+  if (!drhat) return -9;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  double* sdev = h->dev_small + 24;
+  int rc = residual(h->c, n, dA, lda, dx, db, ur, u, drhat, sdev);
+  if (rc) return rc;
+  rc = sync_read(h, sdev, 1);
+  if (rc) return rc;
+  if (s) *s = h->host_small[0];
+  return 0;
+}
+
+int msir_backward_error(msir_handle* h, int n, const double* dA, int lda, const double* dx, const double* db,
+                        double* nbe, double* cbe) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (!dA) return -3;
+  if (lda < n) return -4;
+  if (!dx) return -5;
+  if (!db) return -6;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  double* out = h->dev_small + 28;
+  int rc = norms(h->c, n, dA, lda, db, out);
+  if (rc) return rc;
+  rc = vec_norm_inf(h->c, n, dx, out + 2);
+  if (rc) return rc;
+  rc = backward_errors(h->c, n, dA, lda, dx, db, out + 4);
+  if (rc) return rc;
+  rc = sync_read(h, out, 6);
+  if (rc) return rc;
+  const double* v = h->host_small;
+  const double den = v[0] * v[2] + v[1];
+  if (nbe) *nbe = den > 0 ? v[4] / den : (v[4] > 0 ? INFINITY : 0.0);
+  if (cbe) *cbe = v[5];
+  return 0;
+}
+
+int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, const void* dW, int ldw,
+               const int* dipiv, const double* dR, const double* dS, double mu, const double* drhat, msir_prec u,
+               msir_prec p, double tau, double k_max, int restart, double* dd, int* k) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (!dA) return -3;
+  if (lda < n) return -4;
+  if (f < MSIR_FP16 || f > MSIR_FP64) return -5;
+  if (!dW) return -6;
+  if (ldw < n) return -7;
+  if (!dipiv) return -8;
+  if ((dR == nullptr) != (dS == nullptr)) return -9;
+  if (!drhat) return -12;
+  if (u != MSIR_FP32 && u != MSIR_FP64) return -13;
+  if (!((u == MSIR_FP32 && (p == MSIR_FP32 || p == MSIR_FP64)) || (u == MSIR_FP64 && (p == MSIR_FP64 || p == MSIR_DD))))
+    return -14;
+  if (!(tau > 0)) return -15;
+  if (!(k_max >= 1) || k_max > n) return -16;
+  if (restart < 0) return -17;
+  if (!dd) return -18;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  std::vector<int> piv(n), perm(n);
+  HIP_CHECK(hipMemcpy(piv.data(), dipiv, n * sizeof(int), hipMemcpyDeviceToHost));
+  for (int i = 0; i < n; ++i) perm[i] = i;
+  for (int j = 0; j < n; ++j)
+    if (piv[j] != j) std::swap(perm[j], perm[piv[j]]);
+  int* dperm = (int*)vbuf(h, h->x0, n);
+  double* rinv = vbuf(h, h->xa, n);
+  double* th = vbuf(h, h->tmp_hi, n);
+  double* tl = vbuf(h, h->tmp_lo, n);
+  float* Au = nullptr;
+  if (p == MSIR_FP32) {
+    Au = (float*)h->c.grow(h->Au, (size_t)n * n * sizeof(float));
+    if (!Au) return MSIR_ERR_ALLOC;
+    int rc = to_fp32(h->c, n, dA, lda, Au, n);
+    if (rc) return rc;
+  }
+  if (!dperm || !rinv || !th || !tl) return MSIR_ERR_ALLOC;
+  HIP_CHECK(hipMemcpyAsync(dperm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
+  int rc = diag_reciprocals(h->c, n, f, dW, ldw, rinv);
+  if (rc) return rc;
+  GmresOp op;
+  op.n = n; op.u = u; op.p = p; op.prec = f; op.mode = 0; op.A = dA; op.lda = lda; op.Au = Au; op.W = dW;
+  op.ldw = ldw; op.perm = dperm; op.rinv = rinv; op.R = dR; op.S = dS; op.mu = dR ? mu : 1.0; op.dinv = nullptr;
+  op.tmp_hi = th; op.tmp_lo = tl;
+  int kk = 0;
+  rc = gmres(h->c, h->gw, op, drhat, tau, k_max, restart, dd, &kk);
+  if (rc) return rc;
+  HIP_CHECK(hipStreamSynchronize(h->c.stream));
+  if (k) *k = kk;
+  return 0;
+}
+
+// ------------------------------------------------------------------ Algorithm 4
+static int solve_one(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
+                     const double* dxt, const msir_params& P, msir_result* out, std::vector<msir_step>& hist);
+
+int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx, const double* dxt,
+               const msir_params* params, msir_result* out, msir_step* hist, int hist_cap, int* hist_len) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (!dA) return -3;
+  if (lda < n) return -4;
+  if (!db) return -5;
+  if (!dx) return -6;
+  msir_params P;
+  if (params) P = *params; else msir_params_default(&P);
+  if (P.uf < MSIR_FP16 || P.uf > MSIR_FP64) return -8;
+  if (P.u != MSIR_FP32 && P.u != MSIR_FP64) return -8;
+  if (P.ur != MSIR_FP64 && P.ur != MSIR_DD) return -8;
+  if (P.ux != MSIR_FP64 && P.ux != P.u) return -8;
+  if (P.i_max < 1 || !(P.rho_thresh > 0) || P.restart < 0 || P.max_steps < 1) return -8;
+  if (P.conv == MSIR_CONV_TRUE && !dxt) return -7;
+  if (P.nb != 0 && !nb_ok(n, P.uf, P.nb)) return -8;
+  if (hist_cap < 0) return -11;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  std::vector<msir_step> H;
+  int rc = solve_one(h, n, dA, lda, db, dx, dxt, P, out, H);
+  if (hist_len) *hist_len = (int)H.size();
+  if (hist && hist_cap > 0) memcpy(hist, H.data(), std::min((size_t)hist_cap, H.size()) * sizeof(msir_step));
+  return rc;
+}
+
+static int solve_one(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
+                     const double* dxt, const msir_params& P, msir_result* out, std::vector<msir_step>& hist) {
+  Ctx& c = h->c;
+  int rc;
+  const double k_max = P.k_max > 0 ? P.k_max : 0.1 * n;
+  int uf = P.uf, u = P.u, ur = P.ur;
+  const int ux = P.ux;
+  const int u0 = u;
+  const double uxr = unit_roundoff(ux);
+  const double sqn = sqrt((double)n);
+  auto tau_of = [&](int uu) { return P.tau > 0 ? P.tau : (uu == P_FP32 ? 1e-6 : 1e-10); };
+  const int nb = P.nb;
+
+  double* x0 = vbuf(h, h->x0, n);
+  double* xa = vbuf(h, h->xa, n);
+  double* xb = vbuf(h, h->xb, n);
+  double* rhat = vbuf(h, h->rhat, n);
+  double* d = vbuf(h, h->d, n);
+  double* th = vbuf(h, h->tmp_hi, n);
+  double* tl = vbuf(h, h->tmp_lo, n);
+  if (!x0 || !xa || !xb || !rhat || !d || !th || !tl) return MSIR_ERR_ALLOC;
+  double* ds = h->dev_small;  // [0] s, [1..4] monitors, [8] mu, [16] info, [20] finite, [24..31] misc
+  double* s_dev = ds + 0;
+  double* mon = ds + 32;
+  double* nrm = ds + 40;
+
+  HIP_CHECK(hipEventRecord(h->ev[0], c.stream));
+  rc = norms(c, n, dA, lda, db, nrm);
+  if (rc) return rc;
+  rc = sync_read(h, nrm, 2);
+  if (rc) return rc;
+  const double normA = h->host_small[0], normb = h->host_small[1];
+
+  rc = do_factor(h, n, dA, lda, uf, P.scaling, nb);
+  if (rc) return rc;
+  int n_lu = 1;
+  float* Au = nullptr;
+  if (u == P_FP32) {
+    Au = (float*)c.grow(h->Au, (size_t)n * n * sizeof(float));
+    if (!Au) return MSIR_ERR_ALLOC;
+    rc = to_fp32(c, n, dA, lda, Au, n);
+    if (rc) return rc;
+  }
+  HIP_CHECK(hipEventRecord(h->ev[1], c.stream));
+  float t_factor = 0.0f;
+
+  unsigned ev_pending = h->f.scaled ? MSIR_EV_SCALED : 0u;
+  // x0 by substitution in u_f
+  rc = solve_with(h, n, uf, db, nullptr, x0, -1, 0);
+  if (rc) return rc;
+  rc = vec_norm_inf(c, n, x0, mon);
+  if (rc) return rc;
+  rc = sync_read(h, mon, 2);
+  if (rc) return rc;
+  double x0norm = h->host_small[0];
+  if (h->host_small[1] != 0.0) {
+    HIP_CHECK(hipMemsetAsync(x0, 0, n * sizeof(double), c.stream));
+    ev_pending |= MSIR_EV_NAN_X0;
+    x0norm = 0.0;
+  }
+  if (ux != P_FP64) {
+    rc = round_vec(c, n, x0, x0, ux);
+    if (rc) return rc;
+    rc = vec_norm_inf(c, n, x0, mon);
+    if (rc) return rc;
+    rc = sync_read(h, mon, 1);
+    if (rc) return rc;
+    x0norm = h->host_small[0];
+  }
+  double* x = xa;
+  double* xn = xb;
+  HIP_CHECK(hipMemcpyAsync(x, x0, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+  double xnorm = x0norm;
+  bool have_phi0 = false;
+  double phi0 = 0.0;
+  int alg = 0, it = 0, level = 0, steps = 0, gm_total = 0;
+  double dprev = INFINITY, rho_max = 0.0;
+  bool cached = false;   // rhat/s_dev/s_host describe the current x
+  double s_host = 0.0;
+  bool cged = false;
+  int status = MSIR_NOT_CONVERGED;
+
+  auto nbe_of = [&](double s, double xn_) {
+    const double den = normA * xn_ + normb;
+    return den > 0 ? s / den : (s == 0 ? 0.0 : INFINITY);
+  };
+  auto ferr_of = [&](const double* xx, double* fe) -> int {
+    // max|x - x_true| / max|x_true| via the update kernel: x_new = x + (-1) * x_true
+    double* sm = ds + 60;   // holds -1.0 (set at handle creation)
+    double* mm = ds + 52;
+    int r2 = update_into(c, n, xx, th, dxt, sm, P_FP64, mm);
+    if (r2) return r2;
+    r2 = sync_read(h, mm, 4);
+    if (r2) return r2;
+    const double xt = h->host_small[0], df = h->host_small[2];
+    *fe = xt > 0 ? df / xt : INFINITY;
+    return 0;
+  };
+  auto errors_ok = [&](const double* xx, double s, double xn_, bool* ok) -> int {
+    *ok = false;
+    if (P.conv == MSIR_CONV_BACKWARD) { *ok = nbe_of(s, xn_) <= P.tol_nbe; return 0; }
+    if (P.conv == MSIR_CONV_TRUE) {
+      double fe;
+      int r2 = ferr_of(xx, &fe);
+      if (r2) return r2;
+      *ok = fe <= unit_roundoff(u0) && nbe_of(s, xn_) <= unit_roundoff(u0);
+    }
+    return 0;
+  };
+
+  GmresOp op;
+  op.n = n; op.A = dA; op.lda = lda; op.tmp_hi = th; op.tmp_lo = tl; op.mode = 0; op.dinv = nullptr;
+
+  while (steps < P.max_steps) {
+    if (!cached) {
+      rc = residual(c, n, dA, lda, x, db, ur, u, rhat, s_dev);
+      if (rc) return rc;
+      rc = sync_read(h, s_dev, 1);
+      if (rc) return rc;
+      s_host = h->host_small[0];
+      cached = true;
+    }
+    const double s = s_host;
+    const double nbe_x = isfinite(s) ? nbe_of(s, xnorm) : NAN;
+    if (s == 0.0) { cged = true; status = MSIR_OK; break; }
+    if (P.conv != MSIR_CONV_ESTIMATE && isfinite(s)) {
+      bool ok;
+      rc = errors_ok(x, s, xnorm, &ok);
+      if (rc) return rc;
+      if (ok) { cged = true; status = MSIR_OK; break; }
+    }
+    it += 1;
+    steps += 1;
+    unsigned events = ev_pending;
+    ev_pending = 0;
+    int k = -1;
+    if (alg == 0) {
+      rc = solve_with(h, n, uf, rhat, nullptr, d, u, 0);
+      if (rc) return rc;
+    } else {
+      op.u = u; op.p = (alg == 1) ? u : square_of(u); op.prec = h->f.prec; op.Au = Au;
+      op.W = h->f.W; op.ldw = n; op.perm = h->f.perm; op.rinv = h->f.rinv;
+      op.R = h->f.scaled ? h->f.R : nullptr; op.S = h->f.scaled ? h->f.S : nullptr;
+      op.mu = h->f.scaled ? h->f.mu : 1.0;
+      rc = gmres(c, h->gw, op, rhat, tau_of(u), k_max, P.restart, d, &k);
+      if (rc) return rc;
+      gm_total += k;
+    }
+    rc = update_into(c, n, x, xn, d, s_dev, ux, mon);
+    if (rc) return rc;
+    rc = sync_read(h, mon, 4);
+    if (rc) return rc;
+    const double md = h->host_small[0], mx = h->host_small[1], mxn = h->host_small[2];
+    const bool bad = h->host_small[3] != 0.0;
+    msir_step st;
+    memset(&st, 0, sizeof(st));
+    st.level = level; st.uf = uf; st.u = u; st.ur = ur; st.stage = alg; st.iter = it; st.k_gmres = k;
+    st.counted = 1; st.rnorm = s; st.nbe = nbe_x;
+    if (alg == 0 && bad) {
+      st.z = st.v = st.phi = NAN;
+      st.rho_max = rho_max;
+      st.counted = 0;
+      st.events = events | MSIR_EV_NAN_D | MSIR_EV_SWITCH;
+      hist.push_back(st);
+      alg = 1; it = 0; dprev = INFINITY; rho_max = 0.0;
+      continue;
+    }
+    bool trigger, conv_now = false;
+    double z = NAN, v = NAN, phi = NAN;
+    if (bad) {
+      events |= MSIR_EV_NAN_D;
+      trigger = true;
+    } else {
+      const double delta = s * md;
+      z = mx > 0 ? delta / mx : (delta == 0 ? 0.0 : INFINITY);
+      v = isinf(dprev) ? 0.0 : delta / dprev;
+      rho_max = std::max(rho_max, v);
+      phi = rho_max < 1.0 ? z / (1.0 - rho_max) : INFINITY;
+      if (!have_phi0) { phi0 = phi; have_phi0 = true; }
+      dprev = delta;
+      trigger = z <= uxr || v >= P.rho_thresh || it >= P.i_max || (alg != 0 && k >= k_max) || phi <= sqn * uxr;
+      std::swap(x, xn);
+      xnorm = mxn;
+      cached = false;
+      if (trigger) {
+        if (P.conv == MSIR_CONV_ESTIMATE) {
+          conv_now = 0.0 <= phi && phi <= sqn * uxr;
+        } else {
+          rc = residual(c, n, dA, lda, x, db, ur, u, rhat, s_dev);
+          if (rc) return rc;
+          rc = sync_read(h, s_dev, 1);
+          if (rc) return rc;
+          s_host = h->host_small[0];
+          cached = true;
+          if (isfinite(s_host)) {
+            rc = errors_ok(x, s_host, xnorm, &conv_now);
+            if (rc) return rc;
+          }
+        }
+      }
+    }
+    st.z = z; st.v = v; st.rho_max = rho_max; st.phi = phi; st.events = events;
+    if (trigger && conv_now) {
+      st.events |= MSIR_EV_CONVERGED;
+      hist.push_back(st);
+      cged = true;
+      status = MSIR_OK;
+      break;
+    }
+    if (trigger) {
+      if (have_phi0 && phi > phi0) {
+        HIP_CHECK(hipMemcpyAsync(x, x0, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+        xnorm = x0norm;
+        cached = false;
+        st.events |= MSIR_EV_RESET_X0;
+      }
+      it = 0; dprev = INFINITY; rho_max = 0.0;
+      if (alg == 0) { alg = 1; st.events |= MSIR_EV_SWITCH; }
+      else if (alg == 1) { alg = 2; st.events |= MSIR_EV_SWITCH; }
+      else {
+        st.events |= MSIR_EV_ESCALATE;
+        hist.push_back(st);
+        const int nuf = next_uf(uf);
+        if (nuf < 0) { status = MSIR_NOT_CONVERGED; goto done; }
+        uf = nuf;
+        if (unit_roundoff(uf) < unit_roundoff(u)) u = uf;
+        if (unit_roundoff(ur) > unit_roundoff(u) * unit_roundoff(u)) ur = square_of(u);
+        level += 1;
+        {
+          hipEvent_t e0, e1;
+          (void)e0; (void)e1;
+          rc = do_factor(h, n, dA, lda, uf, P.scaling, nb);
+          if (rc) return rc;
+        }
+        n_lu += 1;
+        ev_pending = h->f.scaled ? MSIR_EV_SCALED : 0u;
+        alg = 0;
+        cached = false;   // u or u_r may have changed: the scaled residual must be recomputed
+        continue;
+      }
+    }
+    hist.push_back(st);
+  }
+done:
+  HIP_CHECK(hipEventRecord(h->ev[2], c.stream));
+  HIP_CHECK(hipMemcpyAsync(dx, x, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    double* eo = ds + 56;
+    rc = vec_norm_inf(c, n, x, eo);
+    if (rc) return rc;
+    rc = backward_errors(c, n, dA, lda, x, db, eo + 2);
+    if (rc) return rc;
+    rc = sync_read(h, eo, 4);
+    if (rc) return rc;
+    const double xf = h->host_small[0], rmax = h->host_small[2], cbe = h->host_small[3];
+    const double den = normA * xf + normb;
+    out->nbe = den > 0 ? rmax / den : (rmax > 0 ? INFINITY : 0.0);
+    out->cbe = cbe;
+    out->ferr = NAN;
+    if (dxt) {
+      double fe;
+      rc = ferr_of(x, &fe);
+      if (rc) return rc;
+      out->ferr = fe;
+    }
+    out->cged = cged ? 1 : 0;
+    out->status = status;
+    out->steps = (int)hist.size();
+    out->n_lu = n_lu;
+    out->gmres_iters = gm_total;
+    out->final_uf = uf; out->final_u = u; out->final_ur = ur;
+    HIP_CHECK(hipEventSynchronize(h->ev[2]));
+    float ms_all = 0.0f, ms_f = 0.0f;
+    (void)hipEventElapsedTime(&ms_f, h->ev[0], h->ev[1]);
+    (void)hipEventElapsedTime(&ms_all, h->ev[0], h->ev[2]);
+    out->t_factor_ms = ms_f;
+    out->t_refine_ms = ms_all - ms_f;
+  }
+  (void)t_factor;
+  HIP_CHECK(hipStreamSynchronize(c.stream));
+  if (!cged && h->f.prec == P_FP64 && h->f.info > 0) status = MSIR_SINGULAR;
+  return status;
+}
+
+int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda, const double* dB, int ldb,
+                     double* dX, int ldx, const msir_params* params, msir_result* outs) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (nrhs < 1) return -3;
+  if (!dA) return -4;
+  if (lda < n) return -5;
+  if (!dB) return -6;
+  if (ldb < n) return -7;
+  if (!dX) return -8;
+  if (ldx < n) return -9;
+  int worst = 0;
+  for (int j = 0; j < nrhs; ++j) {
+    int rc = msir_solve(h, n, dA, lda, dB + (size_t)j * ldb, dX + (size_t)j * ldx, nullptr, params,
+                        outs ? outs + j : nullptr, nullptr, 0, nullptr);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+  }
+  return worst;
+}
+
+int msir_solve_batched(msir_handle* h, int count, const int* n, const double* const* dA, const int* lda,
+                       const double* const* db, double* const* dx, const msir_params* params, msir_result* outs) {
+  if (!h) return -1;
+  if (count < 0) return -2;
+  if (!n || !dA || !lda || !db || !dx) return -3;
+  int worst = 0;
+  for (int i = 0; i < count; ++i) {
+    int rc = msir_solve(h, n[i], dA[i], lda[i], db[i], dx[i], nullptr, params, outs ? outs + i : nullptr, nullptr,
+                        0, nullptr);
+    if (rc < 0) return rc;
+    worst = std::max(worst, rc);
+  }
+  return worst;
+}
+
+}  // extern "C"

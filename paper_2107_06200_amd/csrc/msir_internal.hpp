@@ -1,0 +1,97 @@
+// Internal interfaces of libmsir: the per-handle context (stream, workspace)
+// and the kernels' host launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <string.h>
+#include "../../include/msir.h"
+
+namespace msir {
+
+// A growable device buffer owned by a context.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;       // 0 = unlimited
+  size_t used = 0;
+  // small persistent device state
+  unsigned* counter = nullptr;        // last-block counters (reset by the last block)
+  double* blockmax = nullptr;         // per-block partials of the residual (capacity kMaxBlocks)
+  unsigned long long* tickets = nullptr;  // triangular-solve ticket counter
+  unsigned long long ticket_base = 0;
+  unsigned epoch = 0;
+  double* scalars = nullptr;          // 64 device doubles for small results
+  double* host_pinned = nullptr;      // 64 pinned host doubles
+  DevBuf part_hi, part_lo, r_hi, r_lo, mon_part, flags, yfwd, xbwd, tmp_scalar;
+  static constexpr int kMaxBlocks = 4096;
+  int last_err = 0;
+
+  void* grow(DevBuf& b, size_t bytes);
+  double* ws_part_hi(size_t n) { return (double*)grow(part_hi, n * sizeof(double)); }
+  double* ws_part_lo(size_t n) { return (double*)grow(part_lo, n * sizeof(double)); }
+  double* ws_r_hi(size_t n) { return (double*)grow(r_hi, n * sizeof(double)); }
+  double* ws_r_lo(size_t n) { return (double*)grow(r_lo, n * sizeof(double)); }
+  double* ws_mon_part(size_t n) { return (double*)grow(mon_part, n * sizeof(double)); }
+  double* scratch_scalar(size_t n) { return (double*)grow(tmp_scalar, n * sizeof(double)); }
+  int alloc(void** p, size_t bytes);  // budgeted hipMalloc
+  void release(void* p, size_t bytes);
+};
+
+// ---- launchers (return 0 or an msir status < 0) ----
+int convert(Ctx& c, int n, const double* A, int lda, int prec, const double* R, const double* S, double mu,
+            void* W, int ldw);
+int scaling(Ctx& c, int n, const double* A, int lda, int prec, int rows, double* dR, double* dS, double* dmu,
+            double* dtmp);
+int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
+             double* rhat, double* s_dev);
+int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
+           double* y_hi, double* y_lo, const int* skip);
+int update_into(Ctx& c, int n, const double* x, double* xnew, const double* d, const double* s_dev, int ux,
+                double* mon_dev);
+int norms(Ctx& c, int n, const double* A, int lda, const double* b, double* out_dev);
+int vec_norm_inf(Ctx& c, int n, const double* x, double* out_dev);
+int backward_errors(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, double* out_dev);
+int factors_finite(Ctx& c, int n, int prec, const void* W, int ldw, double* out_dev);
+int diag_reciprocals(Ctx& c, int n, int prec, const void* W, int ldw, double* rinv);
+int to_fp32(Ctx& c, int n, const double* A, int lda, float* Au, int ldau);
+int round_vec(Ctx& c, int n, const double* in, double* out, int p);
+
+int nb_auto(int n, int prec);
+bool nb_ok(int n, int prec, int nb);
+int getrf(Ctx& c, int n, int prec, void* W, int ldw, int nb, int* ipiv, int* info_dev);
+
+// Triangular solve with stored factors.  y = round_out(mu S U^{-1} L^{-1} P R t)
+// with every solution component rounded to comp.  t_lo / y_lo used when comp == DD.
+// in_round: format the permuted, row-scaled right-hand side is rounded to
+// (comp for the u_f-precision solve).  out_round: format of the result (-1: none).
+struct TrsvArgs {
+  int n;
+  int prec;            // factor storage format
+  const void* W;
+  int ldw;
+  const int* perm;     // (P t)[i] = t[perm[i]]
+  const double* rinv;  // 1 / U_ii (float64)
+  const double* R;     // row scaling or null
+  const double* S;     // column scaling or null
+  double mu;
+  int comp;
+  int mode;            // 0 exact substitution in diagonal blocks; 1 inverted diagonal blocks
+  const double* t_hi;
+  const double* t_lo;
+  double* y_hi;
+  double* y_lo;
+  int out_round;
+  const int* skip;     // device flag: nonzero -> the launch does nothing (may be null)
+  const double* dinv;  // inverted diagonal blocks (mode 1)
+};
+int trsv(Ctx& c, const TrsvArgs& a);
+int diag_block_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* dinv);
+size_t diag_inv_doubles(int n);
+
+}  // namespace msir

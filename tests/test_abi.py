@@ -1,0 +1,49 @@
+"""The C ABI library loads and exports every entry point declared in include/msir.h
+(no device calls: this runs without a GPU)."""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "msir.h")
+LIB = os.path.join(ROOT, "paper_2107_06200_amd", "libmsir.so")
+
+
+def declared():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"MSIR_API\s+[\w\s\*]*?\b(msir_\w+)\s*\(", src)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared()
+    for must in ("msir_solve", "msir_solve_multi", "msir_solve_batched", "msir_getrf", "msir_getrs",
+                 "msir_residual", "msir_gmres", "msir_convert", "msir_create", "msir_destroy"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmsir.so not built")
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    L = ctypes.CDLL(LIB)
+    for name in declared():
+        assert hasattr(L, name), name
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmsir.so not built")
+def test_binding_signatures_cover_the_header():
+    from paper_2107_06200_amd import msir as M
+    M.lib()
+    assert sorted(M.SYMBOLS) == declared()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmsir.so not built")
+def test_host_only_calls():
+    # calls that touch no device: defaults, the panel-width rule, status strings
+    from paper_2107_06200_amd import msir as M
+    P = M.params()
+    assert (P.uf, P.u, P.ur, P.ux, P.i_max, P.rho_thresh, P.restart) == (0, 2, 3, 3, 10, 0.5, 0)
+    assert M.nb_auto(100, "fp16") == 64 and M.nb_auto(4096, "fp16") == 16 and M.nb_auto(8192, "fp16") == 8
+    assert M.nb_auto(4096, "fp64") == 8
+    assert M.lib().msir_status_string(0) == b"converged"
+    assert M.workspace_bytes(1000) > 8 * 1000 * 1000

@@ -1,0 +1,293 @@
+"""GPU parity of each step of the hot path against the CPU oracle (same seeded inputs).
+
+Every call goes through the C ABI (paper_2107_06200_amd.msir -> libmsir.so).
+Tolerances, where results are not bit-exact, come from where the two sides
+may round differently: the order of float32 accumulation inside the matrix
+cores (LU trailing update) and the order of float64 accumulation in inner
+products; both are far below the rounding of the stored formats, so most
+outputs agree bit for bit and the rest within a few units of the stored format.
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fmt as F
+from oracle import lu as OLU
+from oracle import ops as OOPS
+from oracle import scaling as OSC
+from oracle import solve as OSV
+from oracle import gmres as OGM
+from paper_2107_06200_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda:0"
+NPDT = {"fp16": np.float16, "fp32": np.float32, "fp64": np.float64}
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2107_06200_amd import msir
+    msir.lib()
+    return msir
+
+
+@pytest.fixture(scope="module")
+def h(M):
+    hh = M.Handle(0)
+    yield hh
+    hh.close()
+
+
+def dev(a, M):
+    return M.colmajor(torch.from_numpy(np.asfortranarray(a)).to(DEV))
+
+
+def tdev(v):
+    return torch.from_numpy(np.ascontiguousarray(v, dtype=np.float64)).to(DEV)
+
+
+def host_w(W, fmt):
+    """Device factor matrix (column-major tensor of the format's dtype) -> float64 numpy."""
+    t = W.t().contiguous().t().cpu()
+    return t.to(torch.float64).numpy()
+
+
+def to_dev_fmt(Wf, fmt, M):
+    t = torch.from_numpy(np.asfortranarray(Wf)).to(M.TORCH_DTYPE[M.PREC[fmt]])
+    return M.colmajor(t.to(DEV))
+
+
+# ------------------------------------------------------------------ conversion
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp32", "fp64"])
+def test_convert_bitexact(M, h, fmt):
+    rng = np.random.default_rng(1)
+    n = 96
+    A = rng.standard_normal((n, n)) * np.exp2(rng.uniform(-30, 20, (n, n)))
+    edge = [65504.0, 65519.99, 65520.0, -65520.0, 2.0 ** -24, 2.0 ** -25, 1.5 * 2.0 ** -25, 3 * 2.0 ** -25,
+            1.0 + 2.0 ** -11, 1.0 + 2.0 ** -11 + 2.0 ** -40, 1.0 + 2.0 ** -8, 1.0 + 2.0 ** -24, np.inf, -np.inf,
+            0.0, -0.0, 1e-300, 3.4e38, 3.5e38]
+    A.flat[: len(edge)] = edge
+    W = M.convert(h, dev(A, M), fmt)
+    got = host_w(W, fmt)
+    want = F.round_to(A, fmt)
+    np.testing.assert_array_equal(got, want)
+
+
+def test_convert_nan_stays_nan(M, h):
+    A = np.ones((8, 8))
+    A[3, 4] = np.nan
+    for fmt in ("fp16", "bf16"):
+        got = host_w(M.convert(h, dev(A, M), fmt), fmt)
+        assert np.isnan(got[3, 4]) and np.isfinite(np.delete(got.ravel(), 4 * 8 + 3)).all()
+
+
+@pytest.mark.parametrize("rows", [True, False])
+def test_scaling_and_scaled_convert_bitexact(M, h, rows):
+    rng = np.random.default_rng(2)
+    n = 130
+    A = rng.standard_normal((n, n)) * np.exp2(rng.integers(-25, 25, (n, 1))) * np.exp2(rng.integers(-10, 10, (1, n)))
+    R, S, mu = M.scaling(h, dev(A, M), "fp16", rows)
+    Ro, So, muo = OSC.compute(A, "fp16", rows=rows)
+    np.testing.assert_array_equal(R, Ro)
+    np.testing.assert_array_equal(S, So)
+    assert mu == muo
+    got = host_w(M.convert(h, dev(A, M), "fp16", R, S, mu), "fp16")
+    np.testing.assert_array_equal(got, F.round_to(OSC.apply(A, Ro, So, muo), "fp16"))
+
+
+# ------------------------------------------------------------------ LU
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp32", "fp64"])
+@pytest.mark.parametrize("n", [1, 5, 32])
+def test_getrf_single_panel_bitexact(M, h, fmt, n):
+    # one panel (nb >= n): the whole factorization is the register-resident panel
+    # kernel, whose arithmetic (fp32 or fp64 FMA, rounded reciprocal) the oracle emulates exactly
+    rng = np.random.default_rng(3 + n)
+    nb = 32
+    Af = F.round_to(rng.standard_normal((n, n)), fmt)
+    W = to_dev_fmt(Af, fmt, M)
+    ipiv, info = M.getrf(h, W, fmt, nb)
+    Wo, po, io = OLU.getrf(Af, fmt, nb)
+    assert info == io
+    np.testing.assert_array_equal(ipiv.cpu().numpy(), po)
+    if fmt == "fp64":
+        np.testing.assert_allclose(host_w(W, fmt), Wo, rtol=0, atol=4e-16 * n * np.abs(Wo).max())
+    else:
+        np.testing.assert_array_equal(host_w(W, fmt), Wo)
+
+
+def manufactured(n, seed):
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(n)
+    A = rng.uniform(-1, 1, (n, n)) * 2.0 ** -8
+    for k, r in enumerate(order):
+        A[r, k] = 2.0 ** (6 - k % 4) * (1 if k % 2 else -1)
+    return A
+
+
+@pytest.mark.parametrize("fmt,n,nb", [("fp16", 300, 64), ("fp16", 1100, 32), ("bf16", 300, 32),
+                                      ("fp32", 257, 16), ("fp64", 200, 16)])
+def test_getrf_manufactured_pivots_bitexact(M, h, fmt, n, nb):
+    Af = F.round_to(manufactured(n, n), fmt)
+    W = to_dev_fmt(Af, fmt, M)
+    ipiv, info = M.getrf(h, W, fmt, nb)
+    Wo, po, io = OLU.getrf(Af, fmt, nb)
+    assert info == io == 0
+    np.testing.assert_array_equal(ipiv.cpu().numpy(), po)
+
+
+@pytest.mark.parametrize("fmt,n,nb", [("fp16", 200, 64), ("fp16", 333, 16), ("bf16", 200, 32),
+                                      ("fp32", 200, 16), ("fp64", 150, 16)])
+def test_getrf_blocked_vs_oracle(M, h, fmt, n, nb):
+    rng = np.random.default_rng(n + nb)
+    Af = F.round_to(rng.standard_normal((n, n)), fmt)
+    W = to_dev_fmt(Af, fmt, M)
+    ipiv, info = M.getrf(h, W, fmt, nb)
+    Wo, po, io = OLU.getrf(Af, fmt, nb)
+    Wg = host_w(W, fmt)
+    piv = ipiv.cpu().numpy()
+    # Backward error of the device factors (Higham): |PA - LU| <= gamma |L||U|
+    L, U = OLU.unpack(Wg)
+    p = OLU.perm_from_piv(piv)
+    E = np.abs(Af[p] - L @ U)
+    g = (n / nb + n * F.u("fp32") / F.u(fmt) + 3) * F.u(fmt)
+    assert np.all(E <= g / (1 - g) * (np.abs(L) @ np.abs(U)) + 1e-300)
+    # agreement with the oracle: the trailing update's float32 accumulation order may
+    # flip a rounding to u_f in a few entries; pivots agree for these random matrices
+    np.testing.assert_array_equal(piv, po)
+    rel = np.abs(Wg - Wo).max() / np.abs(Wo).max()
+    assert rel <= 64 * F.u(fmt), rel
+    frac = np.mean(Wg != Wo)
+    assert frac <= 0.05, frac
+
+
+def test_getrf_zero_pivot_info(M, h):
+    n = 40
+    rng = np.random.default_rng(9)
+    A = F.round_to(rng.standard_normal((n, n)), "fp32")
+    A[:, 7] = 0.0
+    W = to_dev_fmt(A, "fp32", M)
+    ipiv, info = M.getrf(h, W, "fp32", 16)
+    Wo, po, io = OLU.getrf(A, "fp32", 16)
+    assert info == io == 8
+
+
+# ------------------------------------------------------------------ triangular solves
+def oracle_factors(n, fmt, nb, seed, scaled=False):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((n, n)) + 0.0
+    scal = None
+    if scaled:
+        scal = OSC.compute(A, fmt, rows=True)
+        Af = F.round_to(OSC.apply(A, *scal), fmt)
+    else:
+        Af = F.round_to(A, fmt)
+    W, piv, info = OLU.getrf(Af, fmt, nb)
+    return A, W, piv, scal
+
+
+@pytest.mark.parametrize("fmt,comp", [("fp16", "fp16"), ("bf16", "bf16"), ("fp16", "fp32"), ("fp16", "fp64"),
+                                      ("fp32", "fp32"), ("fp32", "fp64"), ("fp64", "fp64")])
+@pytest.mark.parametrize("n", [1, 64, 150])
+@pytest.mark.parametrize("scaled", [False, True])
+def test_getrs_vs_oracle(M, h, fmt, comp, n, scaled):
+    if scaled and fmt != "fp16":
+        pytest.skip("scaling is defined for fp16 factors")
+    A, W, piv, scal = oracle_factors(n, fmt, 16, 11 + n, scaled)
+    t = np.random.default_rng(5).standard_normal(n)
+    want = OSV.lu_solve(W, piv, t, comp, scal)
+    Wd = to_dev_fmt(W, fmt, M)
+    ip = torch.from_numpy(piv.astype(np.int32)).to(DEV)
+    R = S = None
+    mu = 1.0
+    if scal is not None:
+        R, S, mu = tdev(scal[0]), tdev(scal[1]), scal[2]
+    got = M.getrs(h, Wd, fmt, ip, tdev(t), comp, R, S, mu).cpu().numpy()
+    if comp == "fp64":
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+    else:
+        # float64 accumulation on both sides: the component roundings agree unless an
+        # inner product lands within ~1e-16 of a rounding boundary of comp
+        mism = np.mean(got != want)
+        assert mism <= 0.02, mism
+        assert np.abs(got - want).max() <= 64 * F.u(comp) * np.abs(want).max()
+
+
+def test_getrs_dd_vs_oracle(M, h):
+    n = 100
+    A, W, piv, _ = oracle_factors(n, "fp64", 16, 21)
+    t = np.random.default_rng(6).standard_normal(n)
+    hi, lo = OSV.lu_solve(W, piv, t, "dd")
+    Wd = to_dev_fmt(W, "fp64", M)
+    ip = torch.from_numpy(piv.astype(np.int32)).to(DEV)
+    tt = np.concatenate([t, np.zeros(n)])
+    y = M.getrs(h, Wd, "fp64", ip, tdev(tt), "dd").cpu().numpy()
+    # compare hi + lo exactly in double-double terms: |(gh - oh) + (gl - ol)| <= 2^-100 |y|
+    diff = (y[:n] - hi) + (y[n:] - lo)
+    assert np.abs(diff).max() <= 2.0 ** -98 * np.abs(hi).max()
+
+
+def test_getrs_fp16_overflow_gives_inf(M, h):
+    # u_f = fp16 solve: components beyond 65504 become Inf (the Alg. 4 NaN check relies on it)
+    W = np.array([[2.0 ** -10, 0.0], [0.0, 1.0]])
+    Wd = to_dev_fmt(W, "fp16", M)
+    ip = torch.from_numpy(np.arange(2, dtype=np.int32)).to(DEV)
+    y = M.getrs(h, Wd, "fp16", ip, tdev(np.array([100.0, 1.0])), "fp16").cpu().numpy()
+    assert y[0] == np.inf and y[1] == 1.0
+
+
+# ------------------------------------------------------------------ residual
+@pytest.mark.parametrize("ur,u", [("fp64", "fp32"), ("fp64", "fp64"), ("dd", "fp64")])
+@pytest.mark.parametrize("n", [1, 77, 700])
+def test_residual_vs_oracle(M, h, ur, u, n):
+    A, x, b = WL.randsvd(n, 1e4, 3, WL.rng_for(7, n))
+    xh = x + 1e-9 * np.random.default_rng(1).standard_normal(n)
+    r = OOPS.residual(A, xh, b, ur)
+    s = OOPS.rnorm_inf(r)
+    want = OOPS.scale_residual(r, s, u)
+    rhat, sg = M.residual(h, dev(A, M), tdev(xh), tdev(b), ur, u)
+    rg = rhat.cpu().numpy()
+    if ur == "dd":
+        assert abs(sg - s) <= 1e-15 * s
+        mism = np.mean(rg != want)
+        assert mism <= 0.05
+        assert np.abs(rg - want).max() <= 4 * F.u(u)
+    else:
+        # float64 accumulation order differs: |r| agrees to n u_64 |A||x|
+        bound = 4 * n * F.u("fp64") * (np.abs(A) @ np.abs(xh) + np.abs(b)).max()
+        assert abs(sg - s) <= bound
+        assert np.abs(rg * sg - want * s).max() <= bound + 2 * F.u(u) * s
+
+
+def test_backward_error_vs_oracle(M, h):
+    from oracle import metrics as OM
+    n = 300
+    A, x, b = WL.randsvd(n, 1e3, 2, WL.rng_for(8, 0))
+    xh = x * (1 + 1e-12 * np.random.default_rng(2).standard_normal(n))
+    nbe, cbe = M.backward_error(h, dev(A, M), tdev(xh), tdev(b))
+    assert nbe == pytest.approx(OM.nbe(A, xh, b), rel=1e-10)
+    assert cbe == pytest.approx(OM.cbe(A, xh, b), rel=1e-10)
+
+
+# ------------------------------------------------------------------ GMRES
+@pytest.mark.parametrize("u,p,restart", [("fp32", "fp32", 0), ("fp32", "fp64", 0), ("fp32", "fp32", 7),
+                                         ("fp64", "fp64", 0), ("fp64", "dd", 0)])
+def test_gmres_vs_oracle(M, h, u, p, restart):
+    n = 160
+    A, x, b = WL.randsvd(n, 1e5, 3, WL.rng_for(12, 0))
+    Af = F.round_to(A, "fp16")
+    W, piv, _ = OLU.getrf(Af, "fp16", 16)
+    r = b - A @ (x + 1e-3 * np.random.default_rng(3).standard_normal(n))
+    rhat = F.round_to(r / np.abs(r).max(), u)
+    tau = 1e-6 if u == "fp32" else 1e-10
+    dw, kw = OGM.gmres(A, W, piv, None, rhat, u, p, tau, 40, restart)
+    Wd = to_dev_fmt(W, "fp16", M)
+    ip = torch.from_numpy(piv.astype(np.int32)).to(DEV)
+    dg, kg = M.gmres(h, dev(A, M), "fp16", Wd, ip, tdev(rhat), u, p, tau, 40, restart)
+    dg = dg.cpu().numpy()
+    assert abs(kg - kw) <= 1, (kg, kw)
+    tol = 1e-3 if u == "fp32" else 1e-6
+    assert np.abs(dg - dw).max() <= tol * np.abs(dw).max()

@@ -1,0 +1,149 @@
+"""End-to-end parity of Algorithm 4 on the GPU against the CPU oracle.
+
+The oracle runs the same seeded system with the same parameters.  The bar
+(stated for this solver): the same sequence of (precision level, variant,
+number of steps), GMRES counts within +-1, the normwise backward error
+<= 1e-15 (double-double residual), and x within 1e-12 max(1, kappa 1e-4) of
+the oracle's x (relative, inf-norm).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import msir as OM
+from paper_2107_06200_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+@pytest.fixture(scope="module")
+def M():
+    from paper_2107_06200_amd import msir
+    msir.lib()
+    return msir
+
+
+@pytest.fixture(scope="module")
+def h(M):
+    hh = M.Handle(0)
+    yield hh
+    hh.close()
+
+
+def run_both(M, h, A, x, b, **prm):
+    At = M.colmajor(torch.from_numpy(np.asfortranarray(A)).to(DEV))
+    bt = torch.from_numpy(b).to(DEV)
+    xt = torch.from_numpy(x).to(DEV)
+    P = M.params(**prm)
+    xg, res, hist, rc = M.solve(h, At, bt, x_true=xt, P=P)
+    ref = OM.msir(A, b, OM.Params(**prm), x_true=x)
+    return xg.cpu().numpy(), res, hist, rc, ref
+
+
+def summary(hist_levels):
+    return hist_levels
+
+
+def gpu_seq(hist):
+    return [(s.level, s.stage, s.counted, s.k_gmres) for s in hist]
+
+
+def oracle_seq(ref):
+    return [(s.level, s.stage, int(s.counted), s.k) for s in ref.history]
+
+
+def assert_same_history(hist, ref):
+    g = gpu_seq(hist)
+    o = oracle_seq(ref)
+    assert [t[:3] for t in g] == [t[:3] for t in o], (g, o)
+    for a, b in zip(g, o):
+        assert abs(a[3] - b[3]) <= 1, (g, o)
+
+
+def check(M, h, A, x, b, kappa, **prm):
+    xg, res, hist, rc, ref = run_both(M, h, A, x, b, **prm)
+    print("gpu", M.render(hist), "nbe %.2e" % res.nbe, "| oracle", OM.render(ref.history), "nbe %.2e" % ref.nbe)
+    assert_same_history(hist, ref)
+    assert rc == 0 and res.cged == 1
+    assert res.nbe <= 1e-15
+    tol = 1e-12 * max(1.0, kappa * 1e-4)
+    assert np.abs(xg - ref.x).max() <= tol * np.abs(ref.x).max()
+    return res, hist, ref
+
+
+def test_config1_sir(M, h):
+    A, x, b = WL.config_system(1)
+    check(M, h, A, x, b, 1e2, **WL.CONFIGS[1]["params"])
+
+
+@pytest.mark.parametrize("n,kappa,mode", [(65, 1e1, 2), (300, 1e3, 3), (513, 1e2, 2)])
+def test_sir_sizes(M, h, n, kappa, mode):
+    A, x, b = WL.randsvd(n, kappa, mode, WL.rng_for(21, n))
+    check(M, h, A, x, b, kappa, uf="fp16", u="fp32", ur="fp64", i_max=10)
+
+
+@pytest.mark.parametrize("n", [256, 1024])
+def test_multistage_config2_shape(M, h, n):
+    # config 2 scaled down: mode 3, kappa 1e6, column scaling, tau 1e-4, restart 50
+    A, x, b = WL.config_system(2, n=n)
+    res, hist, ref = check(M, h, A, x, b, 1e6, **WL.CONFIGS[2]["params"])
+    assert any(s.stage > 0 for s in hist)
+
+
+def test_gmresir_dd_config3_shape(M, h):
+    # config 3 scaled down: mode 2, kappa 1e10, u = fp64, u_r = double-double
+    A, x, b = WL.config_system(3, n=384)
+    check(M, h, A, x, b, 1e10, **WL.CONFIGS[3]["params"])
+
+
+@pytest.mark.parametrize("uf", ["bf16", "fp32", "fp64"])
+def test_other_factor_formats(M, h, uf):
+    A, x, b = WL.randsvd(200, 1e5, 2, WL.rng_for(22, 0))
+    check(M, h, A, x, b, 1e5, uf=uf, u="fp32" if uf != "fp64" else "fp64", ur="fp64" if uf != "fp64" else "dd")
+
+
+def test_paper_mode_true_convergence(M, h):
+    # u_x = u and the forward/backward error test of the paper's experiments
+    A, x, b = WL.randsvd(100, 1e4, 3, WL.rng_for(23, 0))
+    prm = dict(uf="fp16", u="fp32", ur="fp64", ux="fp32", conv="true", i_max=50, k_max=10)
+    xg, res, hist, rc, ref = run_both(M, h, A, x, b, **prm)
+    assert_same_history(hist, ref)
+    assert rc == ref.status
+
+
+def test_estimate_mode(M, h):
+    A, x, b = WL.randsvd(150, 1e2, 3, WL.rng_for(24, 0))
+    prm = dict(uf="fp32", u="fp64", ur="dd", conv="estimate")
+    xg, res, hist, rc, ref = run_both(M, h, A, x, b, **prm)
+    assert_same_history(hist, ref)
+    assert rc == ref.status
+
+
+def test_nan_input_does_not_converge(M, h):
+    A, x, b = WL.randsvd(70, 1e2, 2, WL.rng_for(25, 0))
+    A[3, 5] = np.nan
+    At = M.colmajor(torch.from_numpy(np.asfortranarray(A)).to(DEV))
+    xg, res, hist, rc = M.solve(h, At, torch.from_numpy(b).to(DEV), P=M.params(max_steps=50))
+    assert rc == 1 and res.cged == 0
+
+
+def test_multi_rhs_and_batched_match_single(M, h):
+    A, X, B = WL.randsvd(120, 1e3, 3, WL.rng_for(26, 0), nrhs=3)
+    At = M.colmajor(torch.from_numpy(np.asfortranarray(A)).to(DEV))
+    Bt = M.colmajor(torch.from_numpy(np.asfortranarray(B)).to(DEV))
+    Xg, outs, rc = M.solve_multi(h, At, Bt)
+    assert rc == 0
+    for j in range(3):
+        xj, res, hist, rcj = M.solve(h, At, Bt[:, j].contiguous())
+        assert torch.equal(xj, Xg[:, j])
+    sys_ = [WL.randsvd(n, 1e2, 2, WL.rng_for(27, n)) for n in (40, 90, 130)]
+    As = [torch.from_numpy(np.asfortranarray(a)).to(DEV) for a, _, _ in sys_]
+    bs = [torch.from_numpy(b).to(DEV) for _, _, b in sys_]
+    xs, outs, rc = M.solve_batched(h, As, bs)
+    assert rc == 0
+    for (a, x, b), xg, o in zip(sys_, xs, outs):
+        assert o.nbe <= 1e-15
+        xi, _, _, _ = M.solve(h, M.colmajor(torch.from_numpy(np.asfortranarray(a)).to(DEV)), torch.from_numpy(b).to(DEV))
+        assert torch.equal(xi, xg)
