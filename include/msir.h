@@ -228,6 +228,27 @@ MSIR_API int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_p
 MSIR_API int msir_backward_error(msir_handle* h, int n, const double* dA, int lda, const double* dx,
                         const double* db, double* nbe, double* cbe);
 
+/* ---- Measurement -------------------------------------------------------------
+ * Per kernel class device time: while enabled, every launch of an instrumented
+ * kernel class on the handle's stream is bracketed by two HIP events; the sum of
+ * their elapsed times and the launch count are kept per class.  Enabling resets
+ * the counters.  Classes: */
+typedef enum {
+    MSIR_T_PANEL = 0,    /* LU panel (pivot search, scaling, rank-1 updates)    */
+    MSIR_T_SWAP = 1,     /* row interchanges + U12 triangular solve              */
+    MSIR_T_GEMM = 2,     /* LU trailing update (matrix cores)                    */
+    MSIR_T_TRSV = 3,     /* forward + backward triangular solve                  */
+    MSIR_T_MATVEC = 4,   /* A v inside GMRES                                     */
+    MSIR_T_RESID = 5,    /* residual b - A x and its scaling                     */
+    MSIR_T_ARNOLDI = 6,  /* modified Gram-Schmidt + Givens                       */
+    MSIR_T_OTHER = 7,
+    MSIR_T_COUNT = 8
+} msir_timer;
+/* enable != 0: start timing (counters reset); 0: stop.                          */
+MSIR_API int msir_timing(msir_handle* h, int enable);
+/* Totals of class `cls` since timing was enabled (synchronizes the stream).     */
+MSIR_API int msir_timing_get(msir_handle* h, int cls, long long* launches, double* total_ms);
+
 #ifdef __cplusplus
 }
 #endif

@@ -136,13 +136,15 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter) {
 }
 
 // ------------------------------------------------------------------ GEMV partials
-// y_part[split][i] = sum_{j in split} A[i, j] x[j]   (TA: double or float matrix;
-// accumulation in double).  DD: hi/lo partials.
-template <typename TA, bool DD>
+// y_part[split][i] = sum_{j in split} A[i, j] x[j] (TA: double or float matrix).
+// MODE 0: float64 fused multiply-add accumulation into part_hi.
+// MODE 1: double-double accumulation (exact products) into part_hi/part_lo.
+// MODE 2: both in one pass over A: float64 into part_x, double-double into hi/lo.
+template <typename TA, int MODE>
 __global__ __launch_bounds__(RT) void k_gemv_part(int n, const TA* __restrict__ A, int lda,
                                                   const double* __restrict__ x, int chunk,
                                                   double* __restrict__ part_hi, double* __restrict__ part_lo,
-                                                  const int* __restrict__ skip) {
+                                                  double* __restrict__ part_x, const int* __restrict__ skip) {
   if (skip && *skip) return;
   const int i = blockIdx.x * RT + threadIdx.x;
   const int s = blockIdx.y;
@@ -150,80 +152,115 @@ __global__ __launch_bounds__(RT) void k_gemv_part(int n, const TA* __restrict__ 
   const int j1 = min(n, j0 + chunk);
   if (i >= n) return;
   const TA* a = A + (size_t)j0 * lda + i;
-  if (!DD) {
-    double acc0 = 0.0, acc1 = 0.0;
+  if (MODE == 0) {
+    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+    int j = j0;
+    for (; j + 3 < j1; j += 4) {
+      const double a0 = (double)a[0], a1 = (double)a[lda], a2 = (double)a[2 * (size_t)lda],
+                   a3 = (double)a[3 * (size_t)lda];
+      acc0 = __fma_rn(a0, x[j], acc0);
+      acc1 = __fma_rn(a1, x[j + 1], acc1);
+      acc2 = __fma_rn(a2, x[j + 2], acc2);
+      acc3 = __fma_rn(a3, x[j + 3], acc3);
+      a += 4 * (size_t)lda;
+    }
+    for (; j < j1; ++j) {
+      acc0 = __fma_rn((double)a[0], x[j], acc0);
+      a += lda;
+    }
+    part_hi[(size_t)s * n + i] = __dadd_rn(__dadd_rn(acc0, acc1), __dadd_rn(acc2, acc3));
+  } else {
+    double h = 0.0, l = 0.0, f = 0.0;
     int j = j0;
     for (; j + 1 < j1; j += 2) {
-      acc0 = __fma_rn((double)a[0], x[j], acc0);
-      acc1 = __fma_rn((double)a[lda], x[j + 1], acc1);
+      const double a0 = (double)a[0], a1 = (double)a[lda];
+      double p, e;
+      two_prod(a0, x[j], p, e);
+      dd_add(h, l, p, e, h, l);
+      two_prod(a1, x[j + 1], p, e);
+      dd_add(h, l, p, e, h, l);
+      if (MODE == 2) { f = __fma_rn(a0, x[j], f); f = __fma_rn(a1, x[j + 1], f); }
       a += 2 * (size_t)lda;
     }
-    if (j < j1) acc0 = __fma_rn((double)a[0], x[j], acc0);
-    part_hi[(size_t)s * n + i] = __dadd_rn(acc0, acc1);
-  } else {
-    double h = 0.0, l = 0.0;
-    for (int j = j0; j < j1; ++j) {
+    for (; j < j1; ++j) {
+      const double a0 = (double)a[0];
       double p, e;
-      two_prod((double)a[0], x[j], p, e);
+      two_prod(a0, x[j], p, e);
       dd_add(h, l, p, e, h, l);
+      if (MODE == 2) f = __fma_rn(a0, x[j], f);
       a += lda;
     }
     part_hi[(size_t)s * n + i] = h;
     part_lo[(size_t)s * n + i] = l;
+    if (MODE == 2) part_x[(size_t)s * n + i] = f;
   }
 }
 
-// Combine partials: out = b - sum (resid) or out = sum; optionally the block max of |out|.
-// Residual mode writes r (hi[, lo]) and, in the last block, s = max|r| and rhat = fl_u(r/s).
-template <bool DD>
+// Combine partials: r = b - sum.  MODE as above.  Writes r (r_hi[, r_lo]) and
+// per-block maxima; the last block folds them into s_out[0] = ||r||_inf of the
+// residual in u_r and s_out[1] = ||r||_inf of the double-double residual (MODE 1, 2),
+// then writes rhat = fl_u(r / s_out[0]) for all rows.
+template <int MODE>
 __global__ __launch_bounds__(RT) void k_resid_finish(int n, int nsplit, const double* __restrict__ part_hi,
-                                                     const double* __restrict__ part_lo, const double* __restrict__ b,
+                                                     const double* __restrict__ part_lo,
+                                                     const double* __restrict__ part_x, const double* __restrict__ b,
                                                      double* __restrict__ r_hi, double* __restrict__ r_lo,
                                                      double* __restrict__ blockmax, unsigned* counter, int u,
                                                      double* __restrict__ rhat, double* __restrict__ s_out) {
   const int i = blockIdx.x * RT + threadIdx.x;
-  double m = 0.0;
-  bool nan = false;
+  double m = 0.0, mt = 0.0;
+  int nan = 0;
   if (i < n) {
-    if (!DD) {
+    if (MODE == 0) {
       double acc = 0.0;
       for (int s = 0; s < nsplit; ++s) acc = __dadd_rn(acc, part_hi[(size_t)s * n + i]);
-      double r = __dsub_rn(b[i], acc);
+      const double r = __dsub_rn(b[i], acc);
       r_hi[i] = r;
       m = fabs(r);
-      nan = !(m == m);
+      mt = m;
     } else {
       double h = b[i], l = 0.0;
       for (int s = 0; s < nsplit; ++s) dd_add(h, l, -part_hi[(size_t)s * n + i], -part_lo[(size_t)s * n + i], h, l);
-      r_hi[i] = h;
-      r_lo[i] = l;
-      double v = __dadd_rn(h, l);
-      m = fabs(v);
-      nan = !(m == m);
+      mt = fabs(__dadd_rn(h, l));
+      if (MODE == 1) {
+        r_hi[i] = h;
+        r_lo[i] = l;
+        m = mt;
+      } else {
+        double acc = 0.0;
+        for (int s = 0; s < nsplit; ++s) acc = __dadd_rn(acc, part_x[(size_t)s * n + i]);
+        const double r = __dsub_rn(b[i], acc);
+        r_hi[i] = r;
+        m = fabs(r);
+      }
     }
+    nan = !(m == m) || !(mt == mt);
   }
-  __shared__ double sh[RT / 64];
+  __shared__ double sh[2][RT / 64];
   __shared__ int shn[RT / 64];
-  double wm = wave_max(m);
-  int wn = wave_or(nan ? 1 : 0);
-  if ((threadIdx.x & 63) == 0) { sh[threadIdx.x >> 6] = wm; shn[threadIdx.x >> 6] = wn; }
+  const double wm = wave_max(m), wt = wave_max(mt);
+  const int wn = wave_or(nan);
+  if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = wm; sh[1][threadIdx.x >> 6] = wt; shn[threadIdx.x >> 6] = wn; }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0; int tn = 0;
-    for (int w = 0; w < RT / 64; ++w) { t = fmax(t, sh[w]); tn |= shn[w]; }
-    blockmax[blockIdx.x] = tn ? __builtin_nan("") : t;
+    double t = 0.0, t2 = 0.0; int tn = 0;
+    for (int w = 0; w < RT / 64; ++w) { t = fmax(t, sh[0][w]); t2 = fmax(t2, sh[1][w]); tn |= shn[w]; }
+    blockmax[2 * blockIdx.x] = tn ? __builtin_nan("") : t;
+    blockmax[2 * blockIdx.x + 1] = tn ? __builtin_nan("") : t2;
   }
   if (!arrive_last(counter)) return;
-  // last block: s = max over blocks (NaN if any NaN), then rhat for all rows
   __shared__ double s_sh;
   if (threadIdx.x == 0) {
-    double t = 0.0; bool tn = false;
+    double t = 0.0, t2 = 0.0; bool tn = false;
     for (int k = 0; k < (int)gridDim.x; ++k) {
-      double v = __hip_atomic_load(&blockmax[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (!(v == v)) tn = true; else t = fmax(t, v);
+      const double v = __hip_atomic_load(&blockmax[2 * k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const double v2 = __hip_atomic_load(&blockmax[2 * k + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (!(v == v) || !(v2 == v2)) tn = true;
+      else { t = fmax(t, v); t2 = fmax(t2, v2); }
     }
     s_sh = tn ? __builtin_nan("") : t;
-    *s_out = s_sh;
+    s_out[0] = s_sh;
+    s_out[1] = tn ? __builtin_nan("") : t2;
     *counter = 0u;
   }
   __syncthreads();
@@ -231,7 +268,7 @@ __global__ __launch_bounds__(RT) void k_resid_finish(int n, int nsplit, const do
   if (rhat) {
     for (int k = threadIdx.x; k < n; k += RT) {
       double q;
-      if (!DD) q = __hip_atomic_load(&r_hi[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / s;
+      if (MODE != 1) q = __hip_atomic_load(&r_hi[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / s;
       else q = __dadd_rn(__hip_atomic_load(&r_hi[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / s,
                          __hip_atomic_load(&r_lo[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) / s);
       rhat[k] = round_to(q, u);
@@ -250,23 +287,29 @@ static int nsplit_for(int n) {
 }
 
 int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
-             double* rhat, double* s_dev) {
+             double* rhat, double* s_dev, bool want_true) {
   const int ns = nsplit_for(n);
   const int chunk = (n + ns - 1) / ns;
   const int rb = (n + RT - 1) / RT;
   double* ph = c.ws_part_hi(ns * (size_t)n);
   double* pl = c.ws_part_lo(ns * (size_t)n);
+  double* px = c.ws_part_x(ns * (size_t)n);
   double* rh = c.ws_r_hi(n);
   double* rl = c.ws_r_lo(n);
-  if (!ph || !pl || !rh || !rl) return MSIR_ERR_ALLOC;
+  if (!ph || !pl || !px || !rh || !rl) return MSIR_ERR_ALLOC;
   dim3 g(rb, ns);
+  const int _slot = c.tbegin(5);
   if (ur == P_DD) {
-    k_gemv_part<double, true><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, nullptr);
-    k_resid_finish<true><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
+    k_gemv_part<double, 1><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, nullptr, nullptr);
+    k_resid_finish<1><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
+  } else if (want_true) {
+    k_gemv_part<double, 2><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, px, nullptr);
+    k_resid_finish<2><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, px, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
   } else {
-    k_gemv_part<double, false><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, nullptr);
-    k_resid_finish<false><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
+    k_gemv_part<double, 0><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, nullptr, nullptr);
+    k_resid_finish<0><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
   }
+  c.tend(_slot);
   HIP_CHECK(hipGetLastError());
   return 0;
 }
@@ -302,16 +345,18 @@ int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, c
   double* pl = c.ws_part_lo(ns * (size_t)n);
   if (!ph || !pl) return MSIR_ERR_ALLOC;
   dim3 g(rb, ns);
+  const int _slot = c.tbegin(4);
   if (p == P_FP32) {
-    k_gemv_part<float, false><<<g, RT, 0, c.stream>>>(n, Au, ldau, v, chunk, ph, pl, skip);
+    k_gemv_part<float, 0><<<g, RT, 0, c.stream>>>(n, Au, ldau, v, chunk, ph, pl, nullptr, skip);
     k_matvec_finish<false><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_FP32, y_hi, y_lo, skip);
   } else if (p == P_FP64) {
-    k_gemv_part<double, false><<<g, RT, 0, c.stream>>>(n, A, lda, v, chunk, ph, pl, skip);
+    k_gemv_part<double, 0><<<g, RT, 0, c.stream>>>(n, A, lda, v, chunk, ph, pl, nullptr, skip);
     k_matvec_finish<false><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_FP64, y_hi, y_lo, skip);
   } else {
-    k_gemv_part<double, true><<<g, RT, 0, c.stream>>>(n, A, lda, v, chunk, ph, pl, skip);
+    k_gemv_part<double, 1><<<g, RT, 0, c.stream>>>(n, A, lda, v, chunk, ph, pl, nullptr, skip);
     k_matvec_finish<true><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_DD, y_hi, y_lo, skip);
   }
+  c.tend(_slot);
   HIP_CHECK(hipGetLastError());
   return 0;
 }
@@ -424,8 +469,8 @@ __global__ __launch_bounds__(RT) void k_errors_finish(int n, int ns, const doubl
 
 int backward_errors(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, double* out_dev) {
   // dd residual into r_hi/r_lo (rhat not needed), then |A||x| partials
-  double* sdev = c.scratch_scalar(1);
-  int rc = residual(c, n, A, lda, x, b, P_DD, P_FP64, nullptr, sdev);
+  double* sdev = c.scratch_scalar(2);
+  int rc = residual(c, n, A, lda, x, b, P_DD, P_FP64, nullptr, sdev, false);
   if (rc) return rc;
   const int ns = nsplit_for(n);
   const int chunk = (n + ns - 1) / ns;

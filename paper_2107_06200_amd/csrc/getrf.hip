@@ -48,7 +48,8 @@ template <int P> __device__ __forceinline__ typename Store<P>::T from_a(double v
 // ------------------------------------------------------------------ panel
 template <int P, int R, int NB>
 __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
-                                               int* __restrict__ ipiv, int* __restrict__ info) {
+                                               int* __restrict__ ipiv, int* __restrict__ info,
+                                               int* __restrict__ moved) {
   typedef typename Arith<P>::T AT;
   typedef typename Store<P>::T ST;
   const int tid = threadIdx.x;
@@ -157,11 +158,90 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
         if (k < jb) W[(size_t)(j0 + k) * ldw + j0 + q] = from_a<P>(a[s][k]);
     }
   }
+  // list of rows that changed position: moved[0] = count, then (dst, src) pairs
+  // (absolute row indices).  The other columns apply the same permutation.
+  __shared__ int s_cnt;
+  if (tid == 0) s_cnt = 0;
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < R; ++s) {
+    const int r = tid + s * PNT;
+    if (valid[s] && pos[s] != r) {
+      const int slot = atomicAdd(&s_cnt, 1);
+      moved[1 + 2 * slot] = j0 + pos[s];
+      moved[2 + 2 * slot] = j0 + r;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) moved[0] = s_cnt;
 }
 
-// ------------------------------------------------------------------ update
-constexpr int SW = 32;    // strip width
-constexpr int UNT = 256;  // update threads
+// ------------------------------------------------------------------ interchanges + U12
+constexpr int SNT = 256;   // one column per thread
+constexpr int MAXMOVE = 128;  // capacity of the moved-row list (at most 2 nb rows move per panel)
+
+// Every column outside the panel gets the panel's row permutation: all moved
+// values are loaded first (independent loads), then stored at their new rows.
+// Columns right of the panel then solve U12 = L11^{-1} A12 by forward
+// substitution (rows in increasing order, fused multiply-adds in the
+// arithmetic format) and store it rounded to u_f.
+template <int P, int KMAX, int MM = 2 * KMAX>
+__global__ __launch_bounds__(SNT) void k_swap_trsm(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0,
+                                                   int jb, const int* __restrict__ moved) {
+  typedef typename Arith<P>::T AT;
+  typedef typename Store<P>::T ST;
+  const int tid = threadIdx.x;
+  const int jr = j0 + jb;
+  __shared__ int sdst[MM], ssrc[MM];
+  __shared__ AT sL[KMAX][KMAX + 1];
+  __shared__ int s_cnt;
+  if (tid == 0) s_cnt = moved[0];
+  __syncthreads();
+  const int cnt = s_cnt;
+  for (int i = tid; i < cnt; i += SNT) { sdst[i] = moved[1 + 2 * i]; ssrc[i] = moved[2 + 2 * i]; }
+  for (int e = tid; e < jb * jb; e += SNT) {
+    const int i = e % jb, k = e / jb;
+    sL[i][k] = to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + i], AT(0));
+  }
+  __syncthreads();
+  // column index: skip the panel columns
+  int col = blockIdx.x * SNT + tid;
+  if (col >= j0) col += jb;
+  if (col >= n) return;
+  ST* w = W + (size_t)col * ldw;
+  ST v[MM];
+#pragma unroll
+  for (int i = 0; i < MM; ++i)
+    if (i < cnt) v[i] = w[ssrc[i]];
+#pragma unroll
+  for (int i = 0; i < MM; ++i)
+    if (i < cnt) w[sdst[i]] = v[i];
+  if (col < jr) return;
+  // same-thread loads after the stores above see the interchanged values
+  AT u[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) u[k] = (k < jb) ? to_a<P>(w[j0 + k], AT(0)) : AT(0);
+#pragma unroll
+  for (int k = 1; k < KMAX; ++k) {
+    if (k < jb) {
+      AT acc = u[k];
+#pragma unroll
+      for (int i = 0; i < KMAX; ++i)
+        if (i < k) acc = a_fma(-sL[k][i], u[i], acc);
+      u[k] = acc;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k)
+    if (k < jb) w[j0 + k] = from_a<P>(u[k]);
+}
+
+// ------------------------------------------------------------------ trailing update
+// A22 <- fl_f(A22 - L21 U12), 64x64 output tile per workgroup (4 waves, 2x2
+// 32x32 MFMA tiles for fp16/bf16; 4x4 register micro-tiles for fp32/fp64).
+// L21 (64 x jb) and U12 (jb x 64) are staged through LDS with coalesced loads.
+constexpr int GT = 64;
+constexpr int GNT = 256;
 
 typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short short4_t __attribute__((ext_vector_type(4)));
@@ -183,161 +263,128 @@ __device__ __forceinline__ float16_t mfma_32x32x8(const uint16_t* a4, const uint
 }
 
 template <int P, int KMAX>
-__global__ __launch_bounds__(UNT) void k_update(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
-                                                const int* __restrict__ ipiv) {
+__global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb) {
   typedef typename Arith<P>::T AT;
   typedef typename Store<P>::T ST;
   const int tid = threadIdx.x;
-  const int c0 = blockIdx.x * SW;
-  const int jr = j0 + jb;  // first trailing column / row
-  __shared__ int spiv[KMAX];
-  __shared__ AT sL[KMAX][KMAX + 1];      // L11 (unit lower), arithmetic format
-  __shared__ ST sU[SW][KMAX + 8];        // U12 (rounded to u_f), [col][k]
-  for (int i = tid; i < jb; i += UNT) spiv[i] = ipiv[j0 + i];
-  const bool has_right = (c0 + SW > jr);
-  if (has_right)
-    for (int e = tid; e < jb * jb; e += UNT) {
-      const int i = e % jb, k = e / jb;
-      sL[i][k] = to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + i], AT(0));
-    }
-  __syncthreads();
-
-  // phase 1: interchanges (all strip columns outside the panel), then U12 for right columns
-  if (tid < SW) {
-    const int col = c0 + tid;
-    const bool in_panel = (col >= j0 && col < jr);
-    if (col < n && !in_panel) {
-      ST* w = W + (size_t)col * ldw;
-      for (int i = 0; i < jb; ++i) {
-        const int p = spiv[i];
-        if (p != j0 + i) {
-          ST t = w[j0 + i];
-          w[j0 + i] = w[p];
-          w[p] = t;
-        }
-      }
-      if (col >= jr) {
-        AT u[KMAX];
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) u[k] = (k < jb) ? to_a<P>(w[j0 + k], AT(0)) : AT(0);
-#pragma unroll
-        for (int k = 1; k < KMAX; ++k) {
-          if (k < jb) {
-            AT acc = u[k];
-#pragma unroll
-            for (int i = 0; i < KMAX; ++i)
-              if (i < k) acc = a_fma(-sL[k][i], u[i], acc);
-            u[k] = acc;
-          }
-        }
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k)
-          if (k < jb) {
-            const ST sv = from_a<P>(u[k]);
-            w[j0 + k] = sv;
-            sU[tid][k] = sv;
-          }
-      } else {
-#pragma unroll
-        for (int k = 0; k < KMAX; ++k) sU[tid][k] = ST(0);
-      }
-    } else {
-      for (int k = 0; k < KMAX; ++k) sU[tid][k] = ST(0);
-    }
+  const int jr = j0 + jb;
+  const int r0 = jr + blockIdx.x * GT;
+  const int c0 = jr + blockIdx.y * GT;
+  __shared__ ST sA[GT][KMAX + 4];   // L21 tile, [row][k]
+  __shared__ ST sB[GT][KMAX + 4];   // U12 tile, [col][k]
+  // stage L21: column k of the tile is 64 contiguous rows
+  for (int e = tid; e < GT * jb; e += GNT) {
+    const int i = e % GT, k = e / GT;
+    const int r = r0 + i;
+    sA[i][k] = (r < n) ? W[(size_t)(j0 + k) * ldw + r] : (ST)0;
   }
-  if (!has_right || jr >= n) return;
+  // stage U12: column c of the tile holds jb contiguous values
+  for (int e = tid; e < GT * jb; e += GNT) {
+    const int k = e % jb, q = e / jb;
+    const int c = c0 + q;
+    sB[q][k] = (c < n) ? W[(size_t)c * ldw + j0 + k] : (ST)0;
+  }
   __syncthreads();
-
-  // phase 2: A22 -= L21 U12 on rows [jr, n), strip columns >= jr
   if constexpr (P == P_FP16 || P == P_BF16) {
     const int lane = tid & 63, wv = tid >> 6;
-    const int lc = lane & 31;       // column within the strip / row within the tile
-    const int hi = lane >> 5;       // k half / row-group half
-    const int col = c0 + lc;
-    const bool col_ok = (col >= jr) && (col < n);
-    for (int r0 = jr + 32 * wv; r0 < n; r0 += 32 * (UNT / 64)) {
-      float16_t acc;
-      // C tile: lane holds column lc, rows 8g + 4hi + e
+    const int lc = lane & 31, hi = lane >> 5;
+    const int tr = (wv & 1) * 32, tc = (wv >> 1) * 32;   // wave's 32x32 sub-tile
+    const int col = c0 + tc + lc;
+    float16_t acc;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + tr + 8 * g + 4 * hi + e;
+        acc[4 * g + e] = (col < n && r < n) ? Store<P>::to_f(W[(size_t)col * ldw + r]) : 0.0f;
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KMAX; kk += 8) {
+      if (kk < jb) {
+        uint16_t a4[4], b4[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          a4[e] = sA[tr + lc][kk + 4 * hi + e] ^ (uint16_t)0x8000;   // -L21 (exact)
+          b4[e] = sB[tc + lc][kk + 4 * hi + e];
+        }
+        acc = mfma_32x32x8<P>(a4, b4, acc);
+      }
+    }
+    if (col < n) {
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int r = r0 + 8 * g + 4 * hi + e;
-          acc[4 * g + e] = (col < n && r < n) ? Store<P>::to_f(W[(size_t)col * ldw + r]) : 0.0f;
+          const int r = r0 + tr + 8 * g + 4 * hi + e;
+          if (r < n) W[(size_t)col * ldw + r] = Store<P>::from_f(acc[4 * g + e]);
         }
-      const int ar = r0 + lc;  // A operand row for this lane
-#pragma unroll
-      for (int kk = 0; kk < KMAX; kk += 8) {
-        if (kk < jb) {
-          uint16_t a4[4], b4[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int k = kk + 4 * hi + e;
-            uint16_t av = (ar < n) ? W[(size_t)(j0 + k) * ldw + ar] : (uint16_t)0;
-            a4[e] = av ^ (uint16_t)0x8000;  // -L21 (sign flip is exact)
-            b4[e] = sU[lc][k];
-          }
-          acc = mfma_32x32x8<P>(a4, b4, acc);
-        }
-      }
-      if (col_ok) {
-#pragma unroll
-        for (int g = 0; g < 4; ++g)
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int r = r0 + 8 * g + 4 * hi + e;
-            if (r < n) W[(size_t)col * ldw + r] = Store<P>::from_f(acc[4 * g + e]);
-          }
-      }
     }
   } else {
-    // fp32 / fp64 factors: one row per thread, SW accumulators
-    for (int r = jr + tid; r < n; r += UNT) {
-      AT acc[SW];
+    // 16 x 16 threads, 4 x 4 outputs each: rows ty + 16 i, columns tx + 16 j
+    const int tx = tid & 15, ty = tid >> 4;
+    AT acc[4][4];
 #pragma unroll
-      for (int q = 0; q < SW; ++q) {
-        const int col = c0 + q;
-        acc[q] = (col >= jr && col < n) ? to_a<P>(W[(size_t)col * ldw + r], AT(0)) : AT(0);
-      }
-      for (int k = 0; k < jb; ++k) {
-        const AT l = to_a<P>(W[(size_t)(j0 + k) * ldw + r], AT(0));
+    for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int q = 0; q < SW; ++q) acc[q] = a_fma(-l, to_a<P>(sU[q][k], AT(0)), acc[q]);
+      for (int j = 0; j < 4; ++j) {
+        const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+        acc[i][j] = (r < n && c < n) ? to_a<P>(W[(size_t)c * ldw + r], AT(0)) : AT(0);
       }
+    for (int k = 0; k < jb; ++k) {
+      AT a[4], b[4];
 #pragma unroll
-      for (int q = 0; q < SW; ++q) {
-        const int col = c0 + q;
-        if (col >= jr && col < n) W[(size_t)col * ldw + r] = from_a<P>(acc[q]);
-      }
+      for (int i = 0; i < 4; ++i) a[i] = to_a<P>(sA[ty + 16 * i][k], AT(0));
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = to_a<P>(sB[tx + 16 * j][k], AT(0));
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = a_fma(-a[i], b[j], acc[i][j]);
     }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
+        if (r < n && c < n) W[(size_t)c * ldw + r] = from_a<P>(acc[i][j]);
+      }
   }
 }
 
 // ------------------------------------------------------------------ driver
 template <int P, int R, int NB>
-static void launch_panel(Ctx& c, void* W, int ldw, int n, int j0, int jb, int* ipiv, int* info) {
-  k_panel<P, R, NB><<<1, PNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, ipiv, info);
+static void launch_panel(Ctx& c, void* W, int ldw, int n, int j0, int jb, int* ipiv, int* info, int* moved) {
+  k_panel<P, R, NB><<<1, PNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, ipiv, info, moved);
 }
 
 template <int P, int NB>
-static void panel_dispatch(Ctx& c, void* W, int ldw, int n, int j0, int jb, int* ipiv, int* info) {
+static void panel_dispatch(Ctx& c, void* W, int ldw, int n, int j0, int jb, int* ipiv, int* info, int* moved) {
   const int m = n - j0;
   const int R = (m + PNT - 1) / PNT;
   constexpr int CAP = (P == P_FP64) ? 32 : 64;  // register values per thread
-  if (R <= 1) launch_panel<P, 1, NB>(c, W, ldw, n, j0, jb, ipiv, info);
-  else if (R <= 2 && 2 * NB <= CAP) launch_panel<P, (2 * NB <= CAP ? 2 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info);
-  else if (R <= 4 && 4 * NB <= CAP) launch_panel<P, (4 * NB <= CAP ? 4 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info);
-  else launch_panel<P, (8 * NB <= CAP ? 8 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info);
+  if (R <= 1) launch_panel<P, 1, NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
+  else if (R <= 2 && 2 * NB <= CAP) launch_panel<P, (2 * NB <= CAP ? 2 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
+  else if (R <= 4 && 4 * NB <= CAP) launch_panel<P, (4 * NB <= CAP ? 4 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
+  else launch_panel<P, (8 * NB <= CAP ? 8 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
 }
 
 template <int P, int NB>
 static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info) {
-  const int nstrips = (n + SW - 1) / SW;
+  int* moved = (int*)c.grow(c.moved, (2 * MAXMOVE + 4) * sizeof(int));
+  if (!moved) return MSIR_ERR_ALLOC;
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = (n - j0 < NB) ? n - j0 : NB;
-    panel_dispatch<P, NB>(c, W, ldw, n, j0, jb, ipiv, info);
-    if (nstrips > 1 || n > jb)
-      k_update<P, NB><<<nstrips, UNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, ipiv);
+    MSIR_TIMED(c, 0, (panel_dispatch<P, NB>(c, W, ldw, n, j0, jb, ipiv, info, moved)));
+    const int others = n - jb;
+    if (others > 0)
+      MSIR_TIMED(c, 1, (k_swap_trsm<P, NB><<<(others + SNT - 1) / SNT, SNT, 0, c.stream>>>(
+                           (typename Store<P>::T*)W, ldw, n, j0, jb, moved)));
+    const int mt = n - j0 - jb;
+    if (mt > 0) {
+      dim3 g((mt + GT - 1) / GT, (mt + GT - 1) / GT);
+      MSIR_TIMED(c, 2, (k_gemm<P, NB><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb)));
+    }
   }
   HIP_CHECK(hipGetLastError());
   return 0;

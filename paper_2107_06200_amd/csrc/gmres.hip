@@ -190,7 +190,8 @@ int gmres(Ctx& c, GmresWork& gw, const GmresOp& op, const double* rhat, double t
     for (int it = 0; it < m; ++it) {
       rc = op.apply_full(c, gw.V + (size_t)it * ldv, gw.w, &st->done);
       if (rc) return rc;
-      k_arnoldi<<<1, GNT, 0, c.stream>>>(n, it, gw.V, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g, gw.beta0, tau, u, st);
+      MSIR_TIMED(c, 6, (k_arnoldi<<<1, GNT, 0, c.stream>>>(n, it, gw.V, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g,
+                                                          gw.beta0, tau, u, st)));
       HIP_CHECK(hipGetLastError());
       if ((it + 1) % CHK == 0 || it + 1 == m) {
         HIP_CHECK(hipMemcpyAsync(gw.host_status, st, sizeof(GStatus), hipMemcpyDeviceToHost, c.stream));

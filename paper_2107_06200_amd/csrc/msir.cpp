@@ -48,6 +48,35 @@ void Ctx::release(void* p, size_t bytes) {
   }
 }
 
+int Ctx::tbegin(int cls) {
+  if (!timing) return -1;
+  if (ev_used + 2 > ev_cap) tflush();
+  if (ev_used + 2 > ev_cap) return -1;
+  const int slot = ev_used;
+  ev_used += 2;
+  ev_cls[slot] = cls;
+  (void)hipEventRecord(ev_pool[slot], stream);
+  return slot;
+}
+
+void Ctx::tend(int slot) {
+  if (slot < 0) return;
+  (void)hipEventRecord(ev_pool[slot + 1], stream);
+}
+
+void Ctx::tflush() {
+  if (ev_used == 0) return;
+  (void)hipStreamSynchronize(stream);
+  for (int i = 0; i < ev_used; i += 2) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ev_pool[i], ev_pool[i + 1]) == hipSuccess) {
+      t_ms[ev_cls[i]] += ms;
+      t_launch[ev_cls[i]] += 1;
+    }
+  }
+  ev_used = 0;
+}
+
 void* Ctx::grow(DevBuf& b, size_t bytes) {
   if (b.bytes >= bytes && b.p) return b.p;
   if (b.p) {
@@ -359,14 +388,19 @@ int msir_destroy(msir_handle* h) {
   (void)hipSetDevice(h->c.device);
   (void)hipStreamSynchronize(h->c.stream);
   Ctx& c = h->c;
-  DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
-                    &c.tmp_scalar, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
+  DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.part_x, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
+                    &c.tmp_scalar, &c.moved, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
                     &h->dinv};
   for (DevBuf* b : bufs) c.release(b->p, b->bytes);
   if (h->f.W) c.release(h->f.W, h->f.Wbytes);
   if (h->f.rinv) c.release(h->f.rinv, h->f.vec_bytes);
   h->gw.free_all(c);
   c.release(c.blockmax, 0);
+  if (c.ev_pool) {
+    for (int i = 0; i < c.ev_cap; ++i) (void)hipEventDestroy(c.ev_pool[i]);
+    delete[] c.ev_pool;
+    delete[] c.ev_cls;
+  }
   c.release(c.counter, 0);
   if (h->host_small) (void)hipHostFree(h->host_small);
   for (int i = 0; i < 4; ++i) (void)hipEventDestroy(h->ev[i]);
@@ -503,7 +537,7 @@ int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double
   if (!drhat) return -9;
   HIP_CHECK(hipSetDevice(h->c.device));
   double* sdev = h->dev_small + 24;
-  int rc = residual(h->c, n, dA, lda, dx, db, ur, u, drhat, sdev);
+  int rc = residual(h->c, n, dA, lda, dx, db, ur, u, drhat, sdev, false);
   if (rc) return rc;
   rc = sync_read(h, sdev, 1);
   if (rc) return rc;
@@ -732,21 +766,24 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
   GmresOp op;
   op.n = n; op.A = dA; op.lda = lda; op.tmp_hi = th; op.tmp_lo = tl; op.mode = 0; op.dinv = nullptr;
 
+  const bool want_true = P.conv != MSIR_CONV_ESTIMATE;
+  double s_true = 0.0;  // inf-norm of the double-double residual (convergence test)
   while (steps < P.max_steps) {
     if (!cached) {
-      rc = residual(c, n, dA, lda, x, db, ur, u, rhat, s_dev);
+      rc = residual(c, n, dA, lda, x, db, ur, u, rhat, s_dev, want_true);
       if (rc) return rc;
-      rc = sync_read(h, s_dev, 1);
+      rc = sync_read(h, s_dev, 2);
       if (rc) return rc;
       s_host = h->host_small[0];
+      s_true = h->host_small[1];
       cached = true;
     }
     const double s = s_host;
     const double nbe_x = isfinite(s) ? nbe_of(s, xnorm) : NAN;
     if (s == 0.0) { cged = true; status = MSIR_OK; break; }
-    if (P.conv != MSIR_CONV_ESTIMATE && isfinite(s)) {
+    if (want_true && isfinite(s_true)) {
       bool ok;
-      rc = errors_ok(x, s, xnorm, &ok);
+      rc = errors_ok(x, s_true, xnorm, &ok);
       if (rc) return rc;
       if (ok) { cged = true; status = MSIR_OK; break; }
     }
@@ -807,14 +844,15 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
         if (P.conv == MSIR_CONV_ESTIMATE) {
           conv_now = 0.0 <= phi && phi <= sqn * uxr;
         } else {
-          rc = residual(c, n, dA, lda, x, db, ur, u, rhat, s_dev);
+          rc = residual(c, n, dA, lda, x, db, ur, u, rhat, s_dev, want_true);
           if (rc) return rc;
-          rc = sync_read(h, s_dev, 1);
+          rc = sync_read(h, s_dev, 2);
           if (rc) return rc;
           s_host = h->host_small[0];
+          s_true = h->host_small[1];
           cached = true;
-          if (isfinite(s_host)) {
-            rc = errors_ok(x, s_host, xnorm, &conv_now);
+          if (isfinite(s_true)) {
+            rc = errors_ok(x, s_true, xnorm, &conv_now);
             if (rc) return rc;
           }
         }
@@ -902,6 +940,32 @@ done:
   HIP_CHECK(hipStreamSynchronize(c.stream));
   if (!cged && h->f.prec == P_FP64 && h->f.info > 0) status = MSIR_SINGULAR;
   return status;
+}
+
+int msir_timing(msir_handle* h, int enable) {
+  if (!h) return -1;
+  Ctx& c = h->c;
+  HIP_CHECK(hipSetDevice(c.device));
+  if (enable && !c.ev_pool) {
+    c.ev_cap = 8192;
+    c.ev_pool = new hipEvent_t[c.ev_cap];
+    c.ev_cls = new int[c.ev_cap];
+    for (int i = 0; i < c.ev_cap; ++i) HIP_CHECK(hipEventCreate(&c.ev_pool[i]));
+  }
+  c.tflush();
+  for (int i = 0; i < 8; ++i) { c.t_ms[i] = 0.0; c.t_launch[i] = 0; }
+  c.timing = enable != 0;
+  return 0;
+}
+
+int msir_timing_get(msir_handle* h, int cls, long long* launches, double* total_ms) {
+  if (!h) return -1;
+  if (cls < 0 || cls >= MSIR_T_COUNT) return -2;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  h->c.tflush();
+  if (launches) *launches = h->c.t_launch[cls];
+  if (total_ms) *total_ms = h->c.t_ms[cls];
+  return 0;
 }
 
 int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda, const double* dB, int ldb,

@@ -28,28 +28,49 @@ struct Ctx {
   unsigned epoch = 0;
   double* scalars = nullptr;          // 64 device doubles for small results
   double* host_pinned = nullptr;      // 64 pinned host doubles
-  DevBuf part_hi, part_lo, r_hi, r_lo, mon_part, flags, yfwd, xbwd, tmp_scalar;
+  DevBuf part_hi, part_lo, part_x, r_hi, r_lo, mon_part, flags, yfwd, xbwd, tmp_scalar, moved;
   static constexpr int kMaxBlocks = 4096;
   int last_err = 0;
 
   void* grow(DevBuf& b, size_t bytes);
   double* ws_part_hi(size_t n) { return (double*)grow(part_hi, n * sizeof(double)); }
   double* ws_part_lo(size_t n) { return (double*)grow(part_lo, n * sizeof(double)); }
+  double* ws_part_x(size_t n) { return (double*)grow(part_x, n * sizeof(double)); }
   double* ws_r_hi(size_t n) { return (double*)grow(r_hi, n * sizeof(double)); }
   double* ws_r_lo(size_t n) { return (double*)grow(r_lo, n * sizeof(double)); }
   double* ws_mon_part(size_t n) { return (double*)grow(mon_part, n * sizeof(double)); }
   double* scratch_scalar(size_t n) { return (double*)grow(tmp_scalar, n * sizeof(double)); }
   int alloc(void** p, size_t bytes);  // budgeted hipMalloc
   void release(void* p, size_t bytes);
+  // per kernel class timing (measurement only)
+  bool timing = false;
+  hipEvent_t* ev_pool = nullptr;
+  int ev_cap = 0, ev_used = 0;
+  int* ev_cls = nullptr;
+  long long t_launch[8] = {0};
+  double t_ms[8] = {0};
+  int tbegin(int cls);           // returns a slot or -1
+  void tend(int slot);
+  void tflush();                 // fold recorded events into the totals
 };
+
+// Bracket a launch with timing events when enabled.
+#define MSIR_TIMED(c, cls, stmt)          \
+  do {                                    \
+    const int _slot = (c).tbegin(cls);    \
+    stmt;                                 \
+    (c).tend(_slot);                      \
+  } while (0)
 
 // ---- launchers (return 0 or an msir status < 0) ----
 int convert(Ctx& c, int n, const double* A, int lda, int prec, const double* R, const double* S, double mu,
             void* W, int ldw);
 int scaling(Ctx& c, int n, const double* A, int lda, int prec, int rows, double* dR, double* dS, double* dmu,
             double* dtmp);
+// r = b - A x in ur; s_dev[0] = ||r||_inf; s_dev[1] = ||r||_inf of the double-double
+// residual when want_true (or ur == DD); rhat = fl_u(r / s_dev[0]) if rhat != null.
 int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
-             double* rhat, double* s_dev);
+             double* rhat, double* s_dev, bool want_true);
 int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
            double* y_hi, double* y_lo, const int* skip);
 int update_into(Ctx& c, int n, const double* x, double* xnew, const double* d, const double* s_dev, int ux,

@@ -252,8 +252,8 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
 
 template <int P>
 static void launch_trsv(Ctx& c, const TrsvK& k, int grid, bool dd) {
-  if (dd) k_trsv<P, true><<<grid, TNT, 0, c.stream>>>(k);
-  else k_trsv<P, false><<<grid, TNT, 0, c.stream>>>(k);
+  if (dd) MSIR_TIMED(c, 3, (k_trsv<P, true><<<grid, TNT, 0, c.stream>>>(k)));
+  else MSIR_TIMED(c, 3, (k_trsv<P, false><<<grid, TNT, 0, c.stream>>>(k)));
 }
 
 int trsv(Ctx& c, const TrsvArgs& a) {

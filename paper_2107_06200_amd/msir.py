@@ -54,7 +54,8 @@ class Result(ctypes.Structure):
 
 SYMBOLS = ["msir_create", "msir_destroy", "msir_params_default", "msir_nb_auto", "msir_workspace_bytes",
            "msir_status_string", "msir_solve", "msir_solve_multi", "msir_solve_batched", "msir_convert",
-           "msir_scaling", "msir_getrf", "msir_getrs", "msir_residual", "msir_gmres", "msir_backward_error"]
+           "msir_scaling", "msir_getrf", "msir_getrs", "msir_residual", "msir_gmres", "msir_backward_error",
+           "msir_timing", "msir_timing_get"]
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -80,7 +81,11 @@ _SIG = {
     "msir_gmres": (_I, [_P, _I, _P, _I, _I, _P, _I, _P, _P, _P, _D, _P, _I, _I, _D, _D, _I, _P,
                         ctypes.POINTER(_I)]),
     "msir_backward_error": (_I, [_P, _I, _P, _I, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
+    "msir_timing": (_I, [_P, _I]),
+    "msir_timing_get": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D)]),
 }
+
+TIMERS = ["panel", "swap", "gemm", "trsv", "matvec", "resid", "arnoldi", "other"]
 
 
 def lib(path=None):
@@ -302,6 +307,21 @@ def backward_error(h, A, x, b):
     _check(lib().msir_backward_error(h.h, n, _ptr(A), _ld(A), _ptr(x), _ptr(b), ctypes.byref(nbe),
                                      ctypes.byref(cbe)), "msir_backward_error")
     return nbe.value, cbe.value
+
+
+def timing(h, enable=True):
+    _check(lib().msir_timing(h.h, 1 if enable else 0), "msir_timing")
+
+
+def timing_get(h):
+    """{class name: (launches, total device ms)} since timing was enabled."""
+    out = {}
+    for i, name in enumerate(TIMERS):
+        c = ctypes.c_longlong(0)
+        t = ctypes.c_double(0)
+        _check(lib().msir_timing_get(h.h, i, ctypes.byref(c), ctypes.byref(t)), "msir_timing_get")
+        out[name] = (c.value, t.value)
+    return out
 
 
 def render(steps):

@@ -206,3 +206,20 @@ def test_scaling_is_power_of_two_and_exact():
     # rows (then columns) have maxima in [1/2, 1) before mu
     RA = np.abs(A) * R[:, None]
     assert np.all((RA.max(axis=1) >= 0.5) & (RA.max(axis=1) < 1))
+
+
+@pytest.mark.parametrize("fmt,n,nb", [("fp16", 100, 16), ("fp32", 70, 8), ("fp64", 50, 4)])
+def test_exact_factors_recovered(fmt, n, nb):
+    # A = P0^T L0 U0 with dyadic multipliers |l| <= 1/2 and a power-of-two diagonal:
+    # all arithmetic is exact, so GEPP must return exactly (P0, L0, U0).
+    rng = np.random.default_rng(n)
+    L0 = np.tril(rng.choice([0.0, 0.25, -0.25, 0.5, -0.5], (n, n)), -1) + np.eye(n)
+    U0 = np.triu(rng.integers(-4, 5, (n, n)).astype(float), 1)
+    U0[np.diag_indices(n)] = rng.choice([1.0, -1.0, 2.0, -2.0, 4.0, -4.0, 8.0, -8.0], n)
+    P0 = rng.permutation(n)
+    A = np.empty((n, n))
+    A[P0] = L0 @ U0
+    W, piv, info = LU.getrf(A, fmt, nb)
+    np.testing.assert_array_equal(W, np.tril(L0, -1) + U0)
+    p = LU.perm_from_piv(piv)
+    np.testing.assert_array_equal(p, P0)
