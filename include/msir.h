@@ -199,9 +199,10 @@ MSIR_API int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, i
  * the GMRES preconditioner), every solution component rounded to `comp`:
  * comp = f is the u_f-precision solve; comp in {FP32, FP64, DD} the operator
  * precision p.  dt, dy: n float64 (for DD, dt and dy point to 2n doubles: hi then
- * lo).  R, S: device arrays or NULL; mu scalar.  mode 0: exact row-by-row
- * substitution inside diagonal blocks; mode 1: diagonal blocks applied through
- * their float64 inverses (faster; differs by rounding).                          */
+ * lo).  R, S: device arrays or NULL; mu scalar.  mode 0: row-by-row substitution
+ * (the definition; components rounded to comp one at a time); mode 1 (comp FP32 or
+ * FP64, ldw == n): through the explicit inverses of L and U, formed in float64 from
+ * the stored factors and rounded to comp, as the GMRES operator applies them.    */
 MSIR_API int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, const int* dipiv,
                const double* dR, const double* dS, double mu, msir_prec comp, int mode,
                const double* dt, double* dy);
@@ -216,7 +217,8 @@ MSIR_API int msir_residual(msir_handle* h, int n, const double* dA, int lda, con
  * M = LU from msir_getrf, operator precision p (FP32: A rounded to fp32; FP64;
  * DD), working precision u, tolerance tau, at most ceil(k_max) iterations, restart
  * length restart (0 = none).  dd: n float64 (u values).  *k receives the number
- * of iterations.  R, S, mu as for msir_getrs.                                     */
+ * of iterations.  R, S, mu as for msir_getrs.  For p in {FP32, FP64} the operator
+ * uses the explicit inverses of L and U (msir_getrs mode 1); for DD substitution. */
 MSIR_API int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, const void* dW,
                int ldw, const int* dipiv, const double* dR, const double* dS, double mu,
                const double* drhat, msir_prec u, msir_prec p, double tau, double k_max,

@@ -39,6 +39,11 @@ struct GmresOp {
   const double* dinv;
   double* tmp_hi;    // n
   double* tmp_lo;    // n
+  double* tmp2;      // n
+  // explicit inverses of L and U in the operator precision (null: substitution)
+  const void* Xinv = nullptr;
+  const void* Yinv = nullptr;
+  int inv_prec = -1;
   // out = fl_u(M^{-1} t), t in u (float64 array); skip: device no-op flag (or null)
   int apply_solve(Ctx& c, const double* t, const int* skip, double* out, const int* unused) const;
   // out = fl_u(M^{-1} (A v)) with A v and the solves in precision p

@@ -142,6 +142,11 @@ void GmresWork::free_all(Ctx& c) {
 }
 
 int GmresOp::apply_solve(Ctx& c, const double* t, const int* skip, double* out, const int*) const {
+  if (Xinv) {
+    int rc = trgemv(c, n, inv_prec, Xinv, 1, t, perm, R, 1.0, nullptr, p, tmp2, skip);
+    if (rc) return rc;
+    return trgemv(c, n, inv_prec, Yinv, 2, tmp2, nullptr, nullptr, mu, S, u, out, skip);
+  }
   TrsvArgs a;
   a.n = n; a.prec = prec; a.W = W; a.ldw = ldw; a.perm = perm; a.rinv = rinv; a.R = R; a.S = S; a.mu = mu;
   a.comp = p; a.mode = mode; a.t_hi = t; a.t_lo = nullptr; a.y_hi = out; a.y_lo = nullptr; a.out_round = u;
@@ -152,6 +157,11 @@ int GmresOp::apply_solve(Ctx& c, const double* t, const int* skip, double* out, 
 int GmresOp::apply_full(Ctx& c, const double* v, double* out, const int* skip) const {
   int rc = matvec(c, n, A, lda, Au, n, v, p, tmp_hi, tmp_lo, skip);
   if (rc) return rc;
+  if (Xinv) {
+    rc = trgemv(c, n, inv_prec, Xinv, 1, tmp_hi, perm, R, 1.0, nullptr, p, tmp2, skip);
+    if (rc) return rc;
+    return trgemv(c, n, inv_prec, Yinv, 2, tmp2, nullptr, nullptr, mu, S, u, out, skip);
+  }
   TrsvArgs a;
   a.n = n; a.prec = prec; a.W = W; a.ldw = ldw; a.perm = perm; a.rinv = rinv; a.R = R; a.S = S; a.mu = mu;
   a.comp = p; a.mode = mode; a.t_hi = tmp_hi; a.t_lo = (p == P_DD) ? tmp_lo : nullptr; a.y_hi = out;
@@ -205,7 +215,8 @@ struct msir_handle {
   Ctx c;
   GmresWork gw;
   FactorState f;
-  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, dinv;
+  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, dinv, Xd, Yd, Xf, Yf, Tinv;
+  bool inv64 = false, inv32 = false;  // inverses of the current factorization are valid
   double* dev_small = nullptr;   // device scalars
   double* host_small = nullptr;  // pinned host scalars
   std::vector<int> hpiv, hperm;
@@ -250,6 +261,7 @@ static int sync_read(msir_handle* h, const double* dev, int count) {
 static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, int scaling_mode, int nb) {
   int rc = ensure_factor(h, n, prec);
   if (rc) return rc;
+  h->inv64 = h->inv32 = false;
   FactorState& f = h->f;
   Ctx& c = h->c;
   double* dmu = h->dev_small + 8;
@@ -304,6 +316,40 @@ static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, 
   rc = diag_reciprocals(c, n, prec, f.W, n, f.rinv);
   if (rc) return rc;
   HIP_CHECK(hipStreamSynchronize(c.stream));
+  return 0;
+}
+
+// Inverses of the current factors in the operator precision p (FP32 or FP64).
+static int ensure_inverses(msir_handle* h, int n, int p, const void** X, const void** Y) {
+  Ctx& c = h->c;
+  if (!h->inv64) {
+    double* Xd = (double*)c.grow(h->Xd, (size_t)n * n * sizeof(double));
+    double* Yd = (double*)c.grow(h->Yd, (size_t)n * n * sizeof(double));
+    double* T = (double*)c.grow(h->Tinv, (size_t)64 * n * sizeof(double));
+    double* dv = (double*)c.grow(h->dinv, (size_t)((n + 63) / 64 + 1) * 64 * 64 * sizeof(double));
+    if (!Xd || !Yd || !T || !dv) return MSIR_ERR_ALLOC;
+    int rc = tri_inverses(c, n, h->f.prec, h->f.W, n, Xd, Yd, T, dv);
+    if (rc) return rc;
+    h->inv64 = true;
+    h->inv32 = false;
+  }
+  if (p == P_FP64) {
+    *X = h->Xd.p;
+    *Y = h->Yd.p;
+    return 0;
+  }
+  if (!h->inv32) {
+    float* Xf = (float*)c.grow(h->Xf, (size_t)n * n * sizeof(float));
+    float* Yf = (float*)c.grow(h->Yf, (size_t)n * n * sizeof(float));
+    if (!Xf || !Yf) return MSIR_ERR_ALLOC;
+    int rc = square_to_f32(c, n, (const double*)h->Xd.p, Xf);
+    if (rc) return rc;
+    rc = square_to_f32(c, n, (const double*)h->Yd.p, Yf);
+    if (rc) return rc;
+    h->inv32 = true;
+  }
+  *X = h->Xf.p;
+  *Y = h->Yf.p;
   return 0;
 }
 
@@ -390,7 +436,7 @@ int msir_destroy(msir_handle* h) {
   Ctx& c = h->c;
   DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.part_x, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
                     &c.tmp_scalar, &c.moved, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
-                    &h->dinv};
+                    &h->tmp2, &h->dinv, &h->Xd, &h->Yd, &h->Xf, &h->Yf, &h->Tinv};
   for (DevBuf* b : bufs) c.release(b->p, b->bytes);
   if (h->f.W) c.release(h->f.W, h->f.Wbytes);
   if (h->f.rinv) c.release(h->f.rinv, h->f.vec_bytes);
@@ -496,7 +542,9 @@ int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, cons
   if (ldw < n) return -5;
   if (!dipiv) return -6;
   if (comp < MSIR_FP16 || comp > MSIR_DD) return -10;
-  if (mode != 0) return -11;
+  if (mode != 0 && mode != 1) return -11;
+  if (mode == 1 && !(comp == MSIR_FP32 || comp == MSIR_FP64)) return -11;
+  if (mode == 1 && ldw != n) return -5;
   if (!dt) return -12;
   if (!dy) return -13;
   HIP_CHECK(hipSetDevice(h->c.device));
@@ -512,10 +560,29 @@ int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, cons
   HIP_CHECK(hipMemcpyAsync(dperm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
   int rc = diag_reciprocals(h->c, n, f, dW, ldw, rinv);
   if (rc) return rc;
+  if ((dR == nullptr) != (dS == nullptr)) return -7;
+  if (mode == 1) {
+    // apply through the explicit inverses of L and U in precision comp
+    const void *X, *Y;
+    FactorState saved = h->f;
+    h->f.prec = f; h->f.W = (void*)dW;
+    h->inv64 = h->inv32 = false;
+    rc = ensure_inverses(h, n, comp, &X, &Y);
+    h->f = saved;
+    h->inv64 = h->inv32 = false;
+    if (rc) return rc;
+    double* t2 = vbuf(h, h->tmp2, n);
+    if (!t2) return MSIR_ERR_ALLOC;
+    rc = trgemv(h->c, n, comp, X, 1, dt, dperm, dR, 1.0, nullptr, comp, t2, nullptr);
+    if (rc) return rc;
+    rc = trgemv(h->c, n, comp, Y, 2, t2, nullptr, nullptr, (dR || dS) ? mu : 1.0, dS, comp, dy, nullptr);
+    if (rc) return rc;
+    HIP_CHECK(hipStreamSynchronize(h->c.stream));
+    return 0;
+  }
   TrsvArgs a;
   a.n = n; a.prec = f; a.W = dW; a.ldw = ldw; a.perm = dperm; a.rinv = rinv; a.R = dR; a.S = dS;
   a.mu = (dR || dS) ? mu : 1.0;
-  if ((dR == nullptr) != (dS == nullptr)) return -7;
   a.comp = comp; a.mode = mode; a.t_hi = dt; a.t_lo = (comp == MSIR_DD) ? dt + n : nullptr;
   a.y_hi = dy; a.y_lo = (comp == MSIR_DD) ? dy + n : nullptr; a.out_round = -1; a.skip = nullptr; a.dinv = nullptr;
   rc = trsv(h->c, a);
@@ -611,10 +678,24 @@ int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, co
   HIP_CHECK(hipMemcpyAsync(dperm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
   int rc = diag_reciprocals(h->c, n, f, dW, ldw, rinv);
   if (rc) return rc;
+  double* t2 = vbuf(h, h->tmp2, n);
+  if (!t2) return MSIR_ERR_ALLOC;
   GmresOp op;
   op.n = n; op.u = u; op.p = p; op.prec = f; op.mode = 0; op.A = dA; op.lda = lda; op.Au = Au; op.W = dW;
   op.ldw = ldw; op.perm = dperm; op.rinv = rinv; op.R = dR; op.S = dS; op.mu = dR ? mu : 1.0; op.dinv = nullptr;
-  op.tmp_hi = th; op.tmp_lo = tl;
+  op.tmp_hi = th; op.tmp_lo = tl; op.tmp2 = t2;
+  if (p != MSIR_DD) {
+    // inverses of the caller's factors (the handle's cached inverses are invalidated)
+    if (ldw != n) return -7;
+    FactorState saved = h->f;
+    h->f.prec = f; h->f.W = (void*)dW;
+    h->inv64 = h->inv32 = false;
+    rc = ensure_inverses(h, n, p, &op.Xinv, &op.Yinv);
+    h->f = saved;
+    h->inv64 = h->inv32 = false;
+    if (rc) return rc;
+    op.inv_prec = p;
+  }
   int kk = 0;
   rc = gmres(h->c, h->gw, op, drhat, tau, k_max, restart, dd, &kk);
   if (rc) return rc;
@@ -763,8 +844,10 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
     return 0;
   };
 
+  double* t2 = vbuf(h, h->tmp2, n);
+  if (!t2) return MSIR_ERR_ALLOC;
   GmresOp op;
-  op.n = n; op.A = dA; op.lda = lda; op.tmp_hi = th; op.tmp_lo = tl; op.mode = 0; op.dinv = nullptr;
+  op.n = n; op.A = dA; op.lda = lda; op.tmp_hi = th; op.tmp_lo = tl; op.tmp2 = t2; op.mode = 0; op.dinv = nullptr;
 
   const bool want_true = P.conv != MSIR_CONV_ESTIMATE;
   double s_true = 0.0;  // inf-norm of the double-double residual (convergence test)
@@ -800,6 +883,13 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
       op.W = h->f.W; op.ldw = n; op.perm = h->f.perm; op.rinv = h->f.rinv;
       op.R = h->f.scaled ? h->f.R : nullptr; op.S = h->f.scaled ? h->f.S : nullptr;
       op.mu = h->f.scaled ? h->f.mu : 1.0;
+      op.Xinv = op.Yinv = nullptr;
+      op.inv_prec = -1;
+      if (op.p != P_DD) {
+        rc = ensure_inverses(h, n, op.p, &op.Xinv, &op.Yinv);
+        if (rc) return rc;
+        op.inv_prec = op.p;
+      }
       rc = gmres(c, h->gw, op, rhat, tau_of(u), k_max, P.restart, d, &k);
       if (rc) return rc;
       gm_total += k;

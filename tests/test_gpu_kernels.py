@@ -322,3 +322,25 @@ def test_gmres_vs_oracle(M, h, u, p, restart):
     assert abs(kg - kw) <= 1, (kg, kw)
     tol = 1e-3 if u == "fp32" else 1e-6
     assert np.abs(dg - dw).max() <= tol * np.abs(dw).max()
+
+
+@pytest.mark.parametrize("comp", ["fp32", "fp64"])
+@pytest.mark.parametrize("n,scaled", [(64, False), (150, True), (300, False)])
+def test_getrs_explicit_inverse_mode(M, h, comp, n, scaled):
+    # mode 1 applies M^{-1} through float64 inverses of L and U rounded to comp: the
+    # same operator as substitution, differing by rounding amplified at most by the
+    # condition numbers of the triangular factors.
+    A, W, piv, scal = oracle_factors(n, "fp16", 16, 40 + n, scaled)
+    t = np.random.default_rng(7).standard_normal(n)
+    want = OSV.lu_solve(W, piv, t, "fp64", scal)
+    Wd = to_dev_fmt(W, "fp16", M)
+    ip = torch.from_numpy(piv.astype(np.int32)).to(DEV)
+    R = S = None
+    mu = 1.0
+    if scal is not None:
+        R, S, mu = tdev(scal[0]), tdev(scal[1]), scal[2]
+    got = M.getrs(h, Wd, "fp16", ip, tdev(t), comp, R, S, mu, mode=1).cpu().numpy()
+    L, U = OLU.unpack(W)
+    kap = np.linalg.cond(L, np.inf) * np.linalg.cond(U, np.inf)
+    rel = np.abs(got - want).max() / np.abs(want).max()
+    assert rel <= 8 * n * kap * F.u(comp), (rel, kap)
