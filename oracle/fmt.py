@@ -89,20 +89,21 @@ def fma32(a, b, c):
     (24 + 24 <= 53 bits); the sum a*b + c is formed exactly as s + e by
     Knuth's TwoSum; the single rounding of s + e to binary32 equals the
     rounding of s unless s is exactly a binary32 midpoint and e != 0, in which
-    case the tie is broken towards the sign of e.
+    case the tie is broken towards the sign of e.  (numpy's float64 -> float32
+    cast is round-to-nearest-even; the tests pin it against rational rounding.)
     """
     a, b, c = np.broadcast_arrays(np.asarray(a, dtype=np.float64),
                                   np.asarray(b, dtype=np.float64),
                                   np.asarray(c, dtype=np.float64))
     shape = a.shape
-    a, b, c = (np.atleast_1d(t).ravel() for t in (a, b, c))
-    p = a * b
-    s = p + c
-    bb = s - p
-    e = (p - (s - bb)) + (c - bb)
-    r = round_to(s, "fp32")
-    with np.errstate(invalid="ignore"):
-        cand = np.isfinite(s) & np.isfinite(r) & (e != 0.0) & (r != s)
+    with np.errstate(all="ignore"):
+        p = a * b
+        s = p + c
+        bb = s - p
+        e = (p - (s - bb)) + (c - bb)
+        r32 = s.astype(np.float32)
+        r = r32.astype(np.float64)
+        cand = (e != 0.0) & (r != s) & np.isfinite(s) & np.isfinite(r)
     if np.any(cand):
         rs, ss, es = r[cand], s[cand], e[cand]
         # the binary32 neighbour of rs on the far side of s
@@ -111,6 +112,5 @@ def fma32(a, b, c):
         is_mid = (ss - rs) == (away - ss)
         lo = np.minimum(rs, away)
         hi = np.maximum(rs, away)
-        fixed = np.where(is_mid, np.where(es > 0, hi, lo), rs)
-        r[cand] = fixed
+        r[cand] = np.where(is_mid, np.where(es > 0, hi, lo), rs)
     return r.reshape(shape)

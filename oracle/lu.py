@@ -43,7 +43,7 @@ def _fma(wa):
     return lambda a, b, c: c + a * b          # float64, two roundings
 
 
-def getrf(A, fmt_f, nb):
+def getrf(A, fmt_f, nb, trailing="fma32"):
     """Factor A (float64, values representable in fmt_f).
 
     Returns (W, piv, info): W holds the unit lower triangle of L below the
@@ -99,7 +99,13 @@ def getrf(A, fmt_f, nb):
             W[j0:j0 + jb, j0 + jb:] = U12
             L21 = W[j0 + jb:, j0:j0 + jb]
             with np.errstate(all="ignore"):
-                W[j0 + jb:, j0 + jb:] = round_to(rnd(W[j0 + jb:, j0 + jb:] - L21 @ U12), fmt_f)
+                if trailing == "fma32" and wa == "fp32":
+                    acc = W[j0 + jb:, j0 + jb:].copy()
+                    for k in range(jb):
+                        acc = fma32(-L21[:, k:k + 1], U12[k:k + 1, :], acc)
+                    W[j0 + jb:, j0 + jb:] = round_to(acc, fmt_f)
+                else:
+                    W[j0 + jb:, j0 + jb:] = round_to(rnd(W[j0 + jb:, j0 + jb:] - L21 @ U12), fmt_f)
     return W, piv, info
 
 

@@ -117,7 +117,9 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
       if (gv < AT(0)) gp = c;  // no valid candidate (all NaN): no interchange
       if (tid == 0) {
         ipiv[j0 + c] = j0 + gp;
-        if (!(gv > AT(0)) && *info == 0) *info = j0 + c + 1;
+        if (!(gv > AT(0))) {
+          if (*info == 0) *info = j0 + c + 1;   // rare path: only then is info read
+        }
       }
       // interchange = relabelling of positions c and gp
 #pragma unroll
@@ -177,7 +179,7 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
 }
 
 // ------------------------------------------------------------------ interchanges + U12
-constexpr int SNT = 256;   // one column per thread
+constexpr int SNT = 64;    // one column per thread, one wave per workgroup
 constexpr int MAXMOVE = 128;  // capacity of the moved-row list (at most 2 nb rows move per panel)
 
 // Every column outside the panel gets the panel's row permutation: all moved
@@ -262,7 +264,7 @@ __device__ __forceinline__ float16_t mfma_32x32x8(const uint16_t* a4, const uint
   }
 }
 
-template <int P, int KMAX>
+template <int P, int KMAX, bool MF>
 __global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb) {
   typedef typename Arith<P>::T AT;
   typedef typename Store<P>::T ST;
@@ -285,18 +287,31 @@ __global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__
     sB[q][k] = (c < n) ? W[(size_t)c * ldw + j0 + k] : (ST)0;
   }
   __syncthreads();
-  if constexpr (P == P_FP16 || P == P_BF16) {
+  if constexpr ((P == P_FP16 || P == P_BF16) && MF) {
     const int lane = tid & 63, wv = tid >> 6;
     const int lc = lane & 31, hi = lane >> 5;
     const int tr = (wv & 1) * 32, tc = (wv >> 1) * 32;   // wave's 32x32 sub-tile
     const int col = c0 + tc + lc;
+    // rows 8g + 4hi + (0..3) are consecutive in a column: one 8-byte access when aligned
+    const bool vec = ((ldw & 3) == 0) && ((r0 & 3) == 0) && (r0 + tr + 32 <= n) && (col < n);
     float16_t acc;
+    if (vec) {
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
+      for (int g = 0; g < 4; ++g) {
+        const uint2 q = *reinterpret_cast<const uint2*>(W + (size_t)col * ldw + r0 + tr + 8 * g + 4 * hi);
+        acc[4 * g + 0] = Store<P>::to_f((uint16_t)(q.x & 0xffffu));
+        acc[4 * g + 1] = Store<P>::to_f((uint16_t)(q.x >> 16));
+        acc[4 * g + 2] = Store<P>::to_f((uint16_t)(q.y & 0xffffu));
+        acc[4 * g + 3] = Store<P>::to_f((uint16_t)(q.y >> 16));
+      }
+    } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int r = r0 + tr + 8 * g + 4 * hi + e;
-        acc[4 * g + e] = (col < n && r < n) ? Store<P>::to_f(W[(size_t)col * ldw + r]) : 0.0f;
+      for (int g = 0; g < 4; ++g) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tr + 8 * g + 4 * hi + e;
+          acc[4 * g + e] = (col < n && r < n) ? Store<P>::to_f(W[(size_t)col * ldw + r]) : 0.0f;
+        }
       }
     }
 #pragma unroll
@@ -311,7 +326,15 @@ __global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__
         acc = mfma_32x32x8<P>(a4, b4, acc);
       }
     }
-    if (col < n) {
+    if (vec) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        uint2 q;
+        q.x = (uint32_t)Store<P>::from_f(acc[4 * g + 0]) | ((uint32_t)Store<P>::from_f(acc[4 * g + 1]) << 16);
+        q.y = (uint32_t)Store<P>::from_f(acc[4 * g + 2]) | ((uint32_t)Store<P>::from_f(acc[4 * g + 3]) << 16);
+        *reinterpret_cast<uint2*>(W + (size_t)col * ldw + r0 + tr + 8 * g + 4 * hi) = q;
+      }
+    } else if (col < n) {
 #pragma unroll
       for (int g = 0; g < 4; ++g)
 #pragma unroll
@@ -370,7 +393,7 @@ static void panel_dispatch(Ctx& c, void* W, int ldw, int n, int j0, int jb, int*
 }
 
 template <int P, int NB>
-static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info) {
+static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info, bool mfma) {
   int* moved = (int*)c.grow(c.moved, (2 * MAXMOVE + 4) * sizeof(int));
   if (!moved) return MSIR_ERR_ALLOC;
   for (int j0 = 0; j0 < n; j0 += NB) {
@@ -383,7 +406,8 @@ static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info) {
     const int mt = n - j0 - jb;
     if (mt > 0) {
       dim3 g((mt + GT - 1) / GT, (mt + GT - 1) / GT);
-      MSIR_TIMED(c, 2, (k_gemm<P, NB><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb)));
+      if (mfma) MSIR_TIMED(c, 2, (k_gemm<P, NB, true><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb)));
+      else MSIR_TIMED(c, 2, (k_gemm<P, NB, false><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb)));
     }
   }
   HIP_CHECK(hipGetLastError());
@@ -409,34 +433,35 @@ bool nb_ok(int n, int prec, int nb) {
 }
 
 template <int P>
-static int getrf_p(Ctx& c, int n, void* W, int ldw, int nb, int* ipiv, int* info) {
+static int getrf_p(Ctx& c, int n, void* W, int ldw, int nb, int* ipiv, int* info, bool mf) {
   if constexpr (P == P_FP64) {
     switch (nb) {
-      case 4: return getrf_nb<P, 4>(c, n, W, ldw, ipiv, info);
-      case 8: return getrf_nb<P, 8>(c, n, W, ldw, ipiv, info);
-      case 16: return getrf_nb<P, 16>(c, n, W, ldw, ipiv, info);
-      case 32: return getrf_nb<P, 32>(c, n, W, ldw, ipiv, info);
+      case 4: return getrf_nb<P, 4>(c, n, W, ldw, ipiv, info, mf);
+      case 8: return getrf_nb<P, 8>(c, n, W, ldw, ipiv, info, mf);
+      case 16: return getrf_nb<P, 16>(c, n, W, ldw, ipiv, info, mf);
+      case 32: return getrf_nb<P, 32>(c, n, W, ldw, ipiv, info, mf);
     }
   } else {
     switch (nb) {
-      case 8: return getrf_nb<P, 8>(c, n, W, ldw, ipiv, info);
-      case 16: return getrf_nb<P, 16>(c, n, W, ldw, ipiv, info);
-      case 32: return getrf_nb<P, 32>(c, n, W, ldw, ipiv, info);
-      case 64: return getrf_nb<P, 64>(c, n, W, ldw, ipiv, info);
+      case 8: return getrf_nb<P, 8>(c, n, W, ldw, ipiv, info, mf);
+      case 16: return getrf_nb<P, 16>(c, n, W, ldw, ipiv, info, mf);
+      case 32: return getrf_nb<P, 32>(c, n, W, ldw, ipiv, info, mf);
+      case 64: return getrf_nb<P, 64>(c, n, W, ldw, ipiv, info, mf);
     }
   }
   return -6;
 }
 
-int getrf(Ctx& c, int n, int prec, void* W, int ldw, int nb, int* ipiv, int* info_dev) {
+int getrf(Ctx& c, int n, int prec, void* W, int ldw, int nb, int* ipiv, int* info_dev, int update) {
+  const bool mf = update == MSIR_LU_MFMA && (prec == P_FP16 || prec == P_BF16);
   if (nb == 0) nb = nb_auto(n, prec);
   if (!nb_ok(n, prec, nb)) return -6;
   HIP_CHECK(hipMemsetAsync(info_dev, 0, sizeof(int), c.stream));
   switch (prec) {
-    case P_FP16: return getrf_p<P_FP16>(c, n, W, ldw, nb, ipiv, info_dev);
-    case P_BF16: return getrf_p<P_BF16>(c, n, W, ldw, nb, ipiv, info_dev);
-    case P_FP32: return getrf_p<P_FP32>(c, n, W, ldw, nb, ipiv, info_dev);
-    case P_FP64: return getrf_p<P_FP64>(c, n, W, ldw, nb, ipiv, info_dev);
+    case P_FP16: return getrf_p<P_FP16>(c, n, W, ldw, nb, ipiv, info_dev, mf);
+    case P_BF16: return getrf_p<P_BF16>(c, n, W, ldw, nb, ipiv, info_dev, mf);
+    case P_FP32: return getrf_p<P_FP32>(c, n, W, ldw, nb, ipiv, info_dev, mf);
+    case P_FP64: return getrf_p<P_FP64>(c, n, W, ldw, nb, ipiv, info_dev, mf);
   }
   return -3;
 }

@@ -67,8 +67,9 @@ __global__ __launch_bounds__(64) void k_trtri_diag(int n, const typename Store<P
 // C[M x N] = beta C + alpha A[M x K] B[K x N]; A of storage type TA, B and C float64,
 // all column-major.  64 x 64 tile per workgroup, 4 x 4 outputs per thread, K in
 // steps of 16 staged through LDS.
-template <typename TA>
-__global__ __launch_bounds__(256) void k_gemm_d(int M, int N, int K, double alpha, const TA* __restrict__ A,
+template <int PA>
+__global__ __launch_bounds__(256) void k_gemm_d(int M, int N, int K, double alpha,
+                                                const typename Store<PA>::T* __restrict__ A,
                                                 int lda, const double* __restrict__ B, int ldb, double beta,
                                                 double* __restrict__ C, int ldc) {
   const int tid = threadIdx.x;
@@ -85,7 +86,7 @@ __global__ __launch_bounds__(256) void k_gemm_d(int M, int N, int K, double alph
     for (int e = tid; e < 16 * 64; e += 256) {
       const int i = e & 63, k = e >> 6;
       const int r = r0 + i, kk = k0 + k;
-      sA[k][i] = (r < M && kk < K) ? (double)A[(size_t)kk * lda + r] : 0.0;
+      sA[k][i] = (r < M && kk < K) ? Store<PA>::to_d(A[(size_t)kk * lda + r]) : 0.0;
     }
     for (int e = tid; e < 16 * 64; e += 256) {
       const int k = e & 15, q = e >> 4;
@@ -133,12 +134,12 @@ __global__ __launch_bounds__(256) void k_copy_block(int rows, int cols, const do
   if (i < rows && j < cols) dst[(size_t)j * ldd + i] = src[(size_t)j * lds + i];
 }
 
-template <typename TA>
-static void gemm_d(Ctx& c, int M, int N, int K, double alpha, const TA* A, int lda, const double* B, int ldb,
-                   double beta, double* C, int ldc) {
+template <int PA>
+static void gemm_d(Ctx& c, int M, int N, int K, double alpha, const typename Store<PA>::T* A, int lda,
+                   const double* B, int ldb, double beta, double* C, int ldc) {
   if (M <= 0 || N <= 0) return;
   dim3 g((M + 63) / 64, (N + 63) / 64);
-  k_gemm_d<TA><<<g, 256, 0, c.stream>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+  k_gemm_d<PA><<<g, 256, 0, c.stream>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
 }
 
 template <int P>
@@ -153,8 +154,8 @@ static int tri_inverses_p(Ctx& c, int n, const void* Wv, int ldw, double* X, dou
   for (int k = 0; k < nblk; ++k) {
     const int r0 = k * IB, rows = std::min(IB, n - r0), cols = r0 + rows;
     k_copy_block<<<dim3(1, cols), 256, 0, c.stream>>>(rows, cols, X + r0, n, T, IB);
-    gemm_d<double>(c, rows, cols, rows, 1.0, dinv + (size_t)k * IB * IB, IB, T, IB, 0.0, X + r0, n);
-    gemm_d<ST>(c, n - r0 - rows, cols, rows, -1.0, W + (size_t)r0 * ldw + r0 + rows, ldw, X + r0, n, 1.0,
+    gemm_d<P_FP64>(c, rows, cols, rows, 1.0, dinv + (size_t)k * IB * IB, IB, T, IB, 0.0, X + r0, n);
+    gemm_d<P>(c, n - r0 - rows, cols, rows, -1.0, W + (size_t)r0 * ldw + r0 + rows, ldw, X + r0, n, 1.0,
                X + r0 + rows, n);
   }
   // U^{-1}
@@ -163,8 +164,8 @@ static int tri_inverses_p(Ctx& c, int n, const void* Wv, int ldw, double* X, dou
   for (int k = nblk - 1; k >= 0; --k) {
     const int r0 = k * IB, rows = std::min(IB, n - r0), cols = n - r0;
     k_copy_block<<<dim3(1, cols), 256, 0, c.stream>>>(rows, cols, Y + (size_t)r0 * n + r0, n, T, IB);
-    gemm_d<double>(c, rows, cols, rows, 1.0, dinv + (size_t)k * IB * IB, IB, T, IB, 0.0, Y + (size_t)r0 * n + r0, n);
-    gemm_d<ST>(c, r0, cols, rows, -1.0, W + (size_t)r0 * ldw, ldw, Y + (size_t)r0 * n + r0, n, 1.0,
+    gemm_d<P_FP64>(c, rows, cols, rows, 1.0, dinv + (size_t)k * IB * IB, IB, T, IB, 0.0, Y + (size_t)r0 * n + r0, n);
+    gemm_d<P>(c, r0, cols, rows, -1.0, W + (size_t)r0 * ldw, ldw, Y + (size_t)r0 * n + r0, n, 1.0,
                Y + (size_t)r0 * n, n);
   }
   HIP_CHECK(hipGetLastError());

@@ -258,7 +258,8 @@ static int sync_read(msir_handle* h, const double* dev, int count) {
 }
 
 // Factor A in u_f = prec with the Sec. 2.1.2 policy.  Leaves factors in h->f.
-static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, int scaling_mode, int nb) {
+static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, int scaling_mode, int nb,
+                     int update) {
   int rc = ensure_factor(h, n, prec);
   if (rc) return rc;
   h->inv64 = h->inv32 = false;
@@ -286,7 +287,7 @@ static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, 
     }
     if (rc) return rc;
     int* dinfo = (int*)(h->dev_small + 16);
-    rc = getrf(c, n, prec, f.W, n, nb, f.ipiv, dinfo);
+    rc = getrf(c, n, prec, f.W, n, nb, f.ipiv, dinfo, update);
     if (rc) return rc;
     if (fp16 && scaling_mode == MSIR_SCALE_AUTO && !use_scaling) {
       rc = factors_finite(c, n, prec, f.W, n, h->dev_small + 20);
@@ -397,6 +398,7 @@ void msir_params_default(msir_params* p) {
   p->scaling = MSIR_SCALE_AUTO;
   p->nb = 0;
   p->max_steps = 1000;
+  p->lu_update = MSIR_LU_MFMA;
 }
 
 int msir_nb_auto(int n, msir_prec fmt) { return nb_auto(n, (int)fmt); }
@@ -513,17 +515,18 @@ int msir_scaling(msir_handle* h, int n, const double* dA, int lda, msir_prec f, 
   return 0;
 }
 
-int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, int nb, int* dipiv, int* info) {
+int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, int nb, int update, int* dipiv, int* info) {
   if (!h) return -1;
   if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
   if (f < MSIR_FP16 || f > MSIR_FP64) return -3;
   if (!dW) return -4;
   if (ldw < n) return -5;
   if (nb != 0 && !nb_ok(n, f, nb)) return -6;
-  if (!dipiv) return -7;
+  if (update != MSIR_LU_MFMA && update != MSIR_LU_FMA) return -7;
+  if (!dipiv) return -8;
   HIP_CHECK(hipSetDevice(h->c.device));
   int* dinfo = (int*)(h->dev_small + 16);
-  int rc = getrf(h->c, n, f, dW, ldw, nb, dipiv, dinfo);
+  int rc = getrf(h->c, n, f, dW, ldw, nb, dipiv, dinfo, update);
   if (rc) return rc;
   int hinfo = 0;
   HIP_CHECK(hipMemcpyAsync(h->host_small, dinfo, sizeof(int), hipMemcpyDeviceToHost, h->c.stream));
@@ -725,6 +728,7 @@ int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* d
   if (P.i_max < 1 || !(P.rho_thresh > 0) || P.restart < 0 || P.max_steps < 1) return -8;
   if (P.conv == MSIR_CONV_TRUE && !dxt) return -7;
   if (P.nb != 0 && !nb_ok(n, P.uf, P.nb)) return -8;
+  if (P.lu_update != MSIR_LU_MFMA && P.lu_update != MSIR_LU_FMA) return -8;
   if (hist_cap < 0) return -11;
   HIP_CHECK(hipSetDevice(h->c.device));
   std::vector<msir_step> H;
@@ -767,7 +771,7 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
   if (rc) return rc;
   const double normA = h->host_small[0], normb = h->host_small[1];
 
-  rc = do_factor(h, n, dA, lda, uf, P.scaling, nb);
+  rc = do_factor(h, n, dA, lda, uf, P.scaling, nb, P.lu_update);
   if (rc) return rc;
   int n_lu = 1;
   float* Au = nullptr;
@@ -978,7 +982,7 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
         {
           hipEvent_t e0, e1;
           (void)e0; (void)e1;
-          rc = do_factor(h, n, dA, lda, uf, P.scaling, nb);
+          rc = do_factor(h, n, dA, lda, uf, P.scaling, nb, P.lu_update);
           if (rc) return rc;
         }
         n_lu += 1;

@@ -85,7 +85,7 @@ int round_vec(Ctx& c, int n, const double* in, double* out, int p);
 
 int nb_auto(int n, int prec);
 bool nb_ok(int n, int prec, int nb);
-int getrf(Ctx& c, int n, int prec, void* W, int ldw, int nb, int* ipiv, int* info_dev);
+int getrf(Ctx& c, int n, int prec, void* W, int ldw, int nb, int* ipiv, int* info_dev, int update);
 
 // Triangular solve with stored factors.  y = round_out(mu S U^{-1} L^{-1} P R t)
 // with every solution component rounded to comp.  t_lo / y_lo used when comp == DD.

@@ -69,6 +69,14 @@ __device__ __forceinline__ void set_flag(unsigned* f, unsigned epoch) {
   __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Broadcast lane `lane`'s value to the wave through scalar registers (lane uniform).
+__device__ __forceinline__ double bcast(double v, int lane) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+
 template <int P, bool DD>
 __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
   typedef typename Store<P>::T ST;
@@ -108,44 +116,71 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
   }
 
   double ph = 0.0, pl = 0.0;
+  // The factor entries of the next off-diagonal block are loaded before waiting for
+  // that block's flag (they do not depend on it); only the solution values wait.
   if (fwd) {
+    double lv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lv[q] = (blk > 0 && rv) ? Store<P>::to_d(W[(size_t)(16 * g + q) * a.ldw + grow]) : 0.0;
     for (int j = 0; j < blk; ++j) {
       if (tid == 0) wait_flag(&a.fflag[j], a.epoch, a.err);
       __syncthreads();
+      double ln[16];
+      const int cn = (j + 1) * TB + 16 * g;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) ln[q] = (j + 1 < blk && rv) ? Store<P>::to_d(W[(size_t)(cn + q) * a.ldw + grow]) : 0.0;
       if (rv) {
         const int cb = j * TB + 16 * g;
-#pragma unroll 4
+#pragma unroll
         for (int q = 0; q < 16; ++q) {
           const int c = cb + q;
-          const double l = Store<P>::to_d(W[(size_t)c * a.ldw + grow]);
           if (!DD) {
-            ph = __fma_rn(l, a.yf_hi[c], ph);
+            ph = __fma_rn(lv[q], a.yf_hi[c], ph);
           } else {
             double p1, p2;
-            dd_mul_d(a.yf_hi[c], a.yf_lo[c], l, p1, p2);
+            dd_mul_d(a.yf_hi[c], a.yf_lo[c], lv[q], p1, p2);
             dd_add(ph, pl, p1, p2, ph, pl);
           }
         }
       }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) lv[q] = ln[q];
     }
   } else {
+    double uv[16];
+    {
+      const int j = nblk - 1;
+      const int cb = j * TB + 16 * g;
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        uv[q] = (j > blk && rv && cb + q < a.n) ? Store<P>::to_d(W[(size_t)(cb + q) * a.ldw + grow]) : 0.0;
+    }
     for (int j = nblk - 1; j > blk; --j) {
       if (tid == 0) wait_flag(&a.bflag[j], a.epoch, a.err);
       __syncthreads();
+      double un[16];
+      const int cn = (j - 1) * TB + 16 * g;
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        un[q] = (j - 1 > blk && rv) ? Store<P>::to_d(W[(size_t)(cn + q) * a.ldw + grow]) : 0.0;
       if (rv) {
         const int cb = j * TB + 16 * g;
-        const int cend = min(cb + 16, a.n);
-        for (int c = cb; c < cend; ++c) {
-          const double u = Store<P>::to_d(W[(size_t)c * a.ldw + grow]);
-          if (!DD) {
-            ph = __fma_rn(u, a.xb_hi[c], ph);
-          } else {
-            double p1, p2;
-            dd_mul_d(a.xb_hi[c], a.xb_lo[c], u, p1, p2);
-            dd_add(ph, pl, p1, p2, ph, pl);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          const int c = cb + q;
+          if (c < a.n) {
+            if (!DD) {
+              ph = __fma_rn(uv[q], a.xb_hi[c], ph);
+            } else {
+              double p1, p2;
+              dd_mul_d(a.xb_hi[c], a.xb_lo[c], uv[q], p1, p2);
+              dd_add(ph, pl, p1, p2, ph, pl);
+            }
           }
         }
       }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) uv[q] = un[q];
     }
     if (tid == 0) wait_flag(&a.fflag[blk], a.epoch, a.err);
   }
@@ -181,10 +216,10 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
       for (int c = 0; c < rows; ++c) {
         double vh, vl = 0.0;
         if (!DD) {
-          vh = __shfl(round_to(ah, a.comp), c, 64);
+          vh = bcast(round_to(ah, a.comp), c);
         } else {
-          vh = __shfl(ah, c, 64);
-          vl = __shfl(al, c, 64);
+          vh = bcast(ah, c);
+          vl = bcast(al, c);
         }
         if (lr == c) { yh = vh; yl = vl; }
         if (lr > c) {
@@ -209,12 +244,12 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
       for (int c = rows - 1; c >= 0; --c) {
         double vh, vl = 0.0;
         if (!DD) {
-          vh = __shfl(round_to(__dmul_rn(ah, ri), a.comp), c, 64);
+          vh = bcast(round_to(__dmul_rn(ah, ri), a.comp), c);
         } else {
           double qh, ql;
           dd_div_d(ah, al, uii, qh, ql);
-          vh = __shfl(qh, c, 64);
-          vl = __shfl(ql, c, 64);
+          vh = bcast(qh, c);
+          vl = bcast(ql, c);
         }
         if (lr == c) { yh = vh; yl = vl; }
         if (lr < c) {

@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
                 ("i_max", ctypes.c_int), ("tau", ctypes.c_double), ("rho_thresh", ctypes.c_double),
                 ("k_max", ctypes.c_double), ("restart", ctypes.c_int), ("conv", ctypes.c_int),
                 ("tol_nbe", ctypes.c_double), ("scaling", ctypes.c_int), ("nb", ctypes.c_int),
-                ("max_steps", ctypes.c_int)]
+                ("max_steps", ctypes.c_int), ("lu_update", ctypes.c_int)]
 
 
 class Step(ctypes.Structure):
@@ -75,7 +75,7 @@ _SIG = {
                                 ctypes.POINTER(Result)]),
     "msir_convert": (_I, [_P, _I, _P, _I, _I, _P, _P, _D, _P, _I]),
     "msir_scaling": (_I, [_P, _I, _P, _I, _I, _I, _P, _P, _P]),
-    "msir_getrf": (_I, [_P, _I, _I, _P, _I, _I, _P, ctypes.POINTER(_I)]),
+    "msir_getrf": (_I, [_P, _I, _I, _P, _I, _I, _I, _P, ctypes.POINTER(_I)]),
     "msir_getrs": (_I, [_P, _I, _I, _P, _I, _P, _P, _P, _D, _I, _I, _P, _P]),
     "msir_residual": (_I, [_P, _I, _P, _I, _P, _P, _I, _I, _P, ctypes.POINTER(_D)]),
     "msir_gmres": (_I, [_P, _I, _P, _I, _I, _P, _I, _P, _P, _P, _D, _P, _I, _I, _D, _D, _I, _P,
@@ -148,6 +148,8 @@ def params(**kw):
             v = CONV[v]
         elif k == "scaling" and isinstance(v, str):
             v = SCALE[v]
+        elif k == "lu_update" and isinstance(v, str):
+            v = {"mfma": 0, "fma": 1}[v]
         setattr(P, k, v)
     return P
 
@@ -258,13 +260,17 @@ def scaling(h, A, fmt, rows=True):
     return R, S, mu.value
 
 
-def getrf(h, W, fmt, nb=0):
+LU_UPDATE = {"mfma": 0, "fma": 1}
+
+
+def getrf(h, W, fmt, nb=0, update="mfma"):
     """In-place LU of W (column-major, format fmt).  Returns (ipiv int32 tensor, info)."""
     assert W.stride(0) == 1
     n = W.shape[0]
     ipiv = torch.empty(n, dtype=torch.int32, device=W.device)
     info = ctypes.c_int(0)
-    _check(lib().msir_getrf(h.h, n, _prec(fmt), _ptr(W), _ld(W), nb, _ptr(ipiv), ctypes.byref(info)), "msir_getrf")
+    _check(lib().msir_getrf(h.h, n, _prec(fmt), _ptr(W), _ld(W), nb, LU_UPDATE[update], _ptr(ipiv),
+                            ctypes.byref(info)), "msir_getrf")
     return ipiv, info.value
 
 

@@ -147,8 +147,8 @@ def test_getrf_blocked_vs_oracle(M, h, fmt, n, nb):
     rng = np.random.default_rng(n + nb)
     Af = F.round_to(rng.standard_normal((n, n)), fmt)
     W = to_dev_fmt(Af, fmt, M)
-    ipiv, info = M.getrf(h, W, fmt, nb)
-    Wo, po, io = OLU.getrf(Af, fmt, nb)
+    ipiv, info = M.getrf(h, W, fmt, nb)   # matrix-core trailing update
+    Wo, po, io = OLU.getrf(Af, fmt, nb, trailing="exact")
     Wg = host_w(W, fmt)
     piv = ipiv.cpu().numpy()
     # Backward error of the device factors (Higham): |PA - LU| <= gamma |L||U|
@@ -187,12 +187,29 @@ def test_getrf_exact_arithmetic_bitexact(M, h, fmt, n, nb):
     A = np.empty((n, n))
     A[P0] = L0 @ U0
     assert np.array_equal(F.round_to(A, fmt), A)
-    W = to_dev_fmt(A, fmt, M)
-    ipiv, info = M.getrf(h, W, fmt, nb)
-    Wo, po, io = OLU.getrf(A, fmt, nb)
+    for update in ("mfma", "fma"):
+        W = to_dev_fmt(A, fmt, M)
+        ipiv, info = M.getrf(h, W, fmt, nb, update=update)
+        Wo, po, io = OLU.getrf(A, fmt, nb)
+        np.testing.assert_array_equal(ipiv.cpu().numpy(), po)
+        np.testing.assert_array_equal(host_w(W, fmt), Wo)
+        np.testing.assert_array_equal(Wo, np.tril(L0, -1) + U0)
+
+
+@pytest.mark.parametrize("fmt,n,nb", [("fp16", 200, 64), ("fp16", 333, 16), ("bf16", 200, 32), ("fp16", 1100, 32),
+                                      ("fp32", 257, 16)])
+def test_getrf_fma_update_bitexact(M, h, fmt, n, nb):
+    """Reproducible trailing update (sequential fp32 FMA over k): the whole blocked
+    factorization -- panel, interchanges, U12, trailing updates -- must equal the
+    oracle's bit for bit, pivots included, on random matrices with ties to break."""
+    rng = np.random.default_rng(7 * n + nb)
+    Af = F.round_to(rng.standard_normal((n, n)), fmt)
+    W = to_dev_fmt(Af, fmt, M)
+    ipiv, info = M.getrf(h, W, fmt, nb, update="fma")
+    Wo, po, io = OLU.getrf(Af, fmt, nb, trailing="fma32")
+    assert info == io
     np.testing.assert_array_equal(ipiv.cpu().numpy(), po)
     np.testing.assert_array_equal(host_w(W, fmt), Wo)
-    np.testing.assert_array_equal(Wo, np.tril(L0, -1) + U0)
 
 
 def test_getrf_zero_pivot_info(M, h):
