@@ -33,6 +33,15 @@ import numpy as np
 from .fmt import fma32, round_to
 
 
+def nb_auto(n, fmt_f):
+    """Default panel width: the panel of the device kernels lives in registers of one
+    compute unit (1024 threads, at most 64 fp32 or 32 fp64 values per thread), so the
+    width is 64 / ceil(n / 1024) rounded down to a power of two, halved for fp64."""
+    R = -(-n // 1024)
+    nb = 64 if R <= 1 else 32 if R <= 2 else 16 if R <= 4 else 8
+    return nb // 2 if fmt_f == "fp64" else nb
+
+
 def arith_format(fmt_f):
     return "fp64" if fmt_f == "fp64" else "fp32"
 
@@ -43,7 +52,7 @@ def _fma(wa):
     return lambda a, b, c: c + a * b          # float64, two roundings
 
 
-def getrf(A, fmt_f, nb, trailing="fma32"):
+def getrf(A, fmt_f, nb=None, trailing="fma32"):
     """Factor A (float64, values representable in fmt_f).
 
     Returns (W, piv, info): W holds the unit lower triangle of L below the
@@ -51,6 +60,8 @@ def getrf(A, fmt_f, nb, trailing="fma32"):
     """
     A = np.asarray(A, dtype=np.float64)
     n = A.shape[0]
+    if nb is None:
+        nb = nb_auto(n, fmt_f)
     W = np.array(A, dtype=np.float64, order="F", copy=True)
     piv = np.arange(n, dtype=np.int64)
     info = 0

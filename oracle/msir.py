@@ -73,8 +73,9 @@ class Params:
     conv: str = "backward"               # 'estimate' | 'backward' | 'true'
     tol_nbe: float = 1e-15
     scaling: str = "auto"                # 'never' | 'auto' | 'always' | 'cols'
-    nb: int = 16
+    nb: Optional[int] = None            # None: the default width rule of oracle.lu.nb_auto
     max_steps: int = 1000
+    lu_trailing: str = "fma32"          # 'fma32' | 'exact' (see oracle.lu.getrf)
 
 
 @dataclass
@@ -122,7 +123,7 @@ def square(uu):
     return {"fp32": "fp64", "fp64": "dd"}[uu]
 
 
-def factor(A, uf, scaling_mode, nb):
+def factor(A, uf, scaling_mode, nb, trailing="fma32"):
     """Alg. 4 first line with the Sec. 2.1.2 retry.  Returns (W, piv, info, scal, scaled)."""
     scal = None
     use_scaling = uf == "fp16" and scaling_mode in ("always", "cols")
@@ -131,11 +132,11 @@ def factor(A, uf, scaling_mode, nb):
         Af = F.round_to(SC.apply(A, *scal), uf)
     else:
         Af = F.round_to(A, uf)
-    W, piv, info = LU.getrf(Af, uf, nb)
+    W, piv, info = LU.getrf(Af, uf, nb, trailing)
     if uf == "fp16" and scaling_mode == "auto" and not np.all(np.isfinite(W)):
         scal = SC.compute(A, uf, rows=True)
         Af = F.round_to(SC.apply(A, *scal), uf)
-        W, piv, info = LU.getrf(Af, uf, nb)
+        W, piv, info = LU.getrf(Af, uf, nb, trailing)
     return W, piv, info, scal
 
 
@@ -184,7 +185,7 @@ def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None):
     level = 0
     n_lu = 1
 
-    W, piv, info, scal = factor(A, uf, P.scaling, P.nb)
+    W, piv, info, scal = factor(A, uf, P.scaling, P.nb, P.lu_trailing)
     ev_scaled = EV_SCALED if scal is not None else 0
     x0 = lu_solve(W, piv, b, uf, scal)
     ev_pending = ev_scaled
@@ -316,7 +317,7 @@ def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None):
                 if F.u(ur) > F.u(u) ** 2:
                     ur = square(u)
                 level += 1
-                W, piv, info, scal = factor(A, uf, P.scaling, P.nb)
+                W, piv, info, scal = factor(A, uf, P.scaling, P.nb, P.lu_trailing)
                 n_lu += 1
                 ev_pending = EV_SCALED if scal is not None else 0
                 alg = SIR

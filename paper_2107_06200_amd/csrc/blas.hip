@@ -22,6 +22,7 @@
 namespace msir {
 
 constexpr int RT = 256;  // rows per workgroup (one per thread)
+constexpr int kMaxChunk = 512;  // columns per workgroup at most
 
 // ------------------------------------------------------------------ conversion
 template <int P>
@@ -150,6 +151,12 @@ __global__ __launch_bounds__(RT) void k_gemv_part(int n, const TA* __restrict__ 
   const int s = blockIdx.y;
   const int j0 = s * chunk;
   const int j1 = min(n, j0 + chunk);
+  // this workgroup's slice of x, read once into LDS (avoids a dependent global
+  // load per column in the inner loop)
+  __shared__ double sx[kMaxChunk];
+  for (int t = threadIdx.x; t < j1 - j0; t += RT) sx[t] = x[j0 + t];
+  __syncthreads();
+  x = sx - j0;
   if (i >= n) return;
   const TA* a = A + (size_t)j0 * lda + i;
   if (MODE == 0) {
@@ -282,6 +289,8 @@ static int nsplit_for(int n) {
   int s = (1024 + rb - 1) / rb;
   int maxs = (n + 31) / 32;     // at least 32 columns per split
   if (s > maxs) s = maxs;
+  const int mins = (n + kMaxChunk - 1) / kMaxChunk;
+  if (s < mins) s = mins;
   if (s < 1) s = 1;
   return s;
 }

@@ -47,35 +47,57 @@ __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restric
                                                  double* __restrict__ g, const double* __restrict__ beta0, double tau,
                                                  int u, GStatus* st) {
   if (st->done) return;
-  __shared__ double sh[GNT / 64];
+  // partial sums of each wave, double-buffered by the parity of the dot index so that
+  // one barrier per inner product suffices
+  __shared__ double sh[2][GNT / 64];
   __shared__ double s_hn;
   const int tid = threadIdx.x;
-  double w[GPT];
+  const int lane = tid & 63, wv = tid >> 6;
+  double w[GPT], v[GPT];
 #pragma unroll
   for (int t = 0; t < GPT; ++t) {
-    const int i = tid + t * GNT;
-    w[t] = i < n ? w_in[i] : 0.0;
+    const int r = tid + t * GNT;
+    w[t] = r < n ? w_in[r] : 0.0;
+    v[t] = r < n ? V[r] : 0.0;
   }
   for (int i = 0; i <= j; ++i) {
-    const double* v = V + (size_t)i * ldv;
+    // next basis vector in flight while this inner product is reduced
+    double vn[GPT];
+    const double* vnp = V + (size_t)(i + 1) * ldv;
+#pragma unroll
+    for (int t = 0; t < GPT; ++t) {
+      const int r = tid + t * GNT;
+      vn[t] = (i < j && r < n) ? vnp[r] : 0.0;
+    }
     double acc = 0.0;
 #pragma unroll
-    for (int t = 0; t < GPT; ++t) {
-      const int r = tid + t * GNT;
-      if (r < n) acc = __fma_rn(v[r], w[t], acc);
-    }
-    const double h = block_sum<GNT>(acc, sh);
+    for (int t = 0; t < GPT; ++t) acc = __fma_rn(v[t], w[t], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) sh[i & 1][wv] = acc;
+    __syncthreads();
+    double h = 0.0;
+#pragma unroll
+    for (int q = 0; q < GNT / 64; ++q) h = __dadd_rn(h, sh[i & 1][q]);
 #pragma unroll
     for (int t = 0; t < GPT; ++t) {
       const int r = tid + t * GNT;
-      if (r < n) w[t] = round_to(__dsub_rn(w[t], __dmul_rn(h, v[r])), u);
+      if (r < n) w[t] = round_to(__dsub_rn(w[t], __dmul_rn(h, v[t])), u);
     }
     if (tid == 0) H[(size_t)j * ldh + i] = h;
+#pragma unroll
+    for (int t = 0; t < GPT; ++t) v[t] = vn[t];
   }
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < GPT; ++t) acc = __fma_rn(w[t], w[t], acc);
-  const double hn = sqrt(block_sum<GNT>(acc, sh));
+  acc = wave_sum(acc);
+  const int pb = (j + 1) & 1;
+  if (lane == 0) sh[pb][wv] = acc;
+  __syncthreads();
+  double nn = 0.0;
+#pragma unroll
+  for (int q = 0; q < GNT / 64; ++q) nn = __dadd_rn(nn, sh[pb][q]);
+  const double hn = sqrt(nn);
   if (tid == 0) {
     double* hc = H + (size_t)j * ldh;
     hc[j + 1] = hn;
@@ -98,15 +120,12 @@ __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restric
     const bool stop = !__builtin_isfinite(g[j + 1]) || e <= tau * (*beta0) || hn == 0.0;
     st->jcount = j + 1;
     st->done = stop ? 1 : 0;
-    s_hn = hn;
   }
-  __syncthreads();
-  const double hh = s_hn;
-  double* vn = V + (size_t)(j + 1) * ldv;
+  double* vnx = V + (size_t)(j + 1) * ldv;
 #pragma unroll
   for (int t = 0; t < GPT; ++t) {
     const int r = tid + t * GNT;
-    if (r < n) vn[r] = round_to(w[t] / hh, u);
+    if (r < n) vnx[r] = round_to(w[t] / hn, u);
   }
 }
 

@@ -202,6 +202,7 @@ int square_to_f32(Ctx& c, int n, const double* X, float* Xf) {
 // workgroup of each 256-row block (per-block counter) sums the partials in split
 // order, so results are reproducible.
 constexpr int TRT = 256;
+constexpr int kTrChunk = 512;
 
 template <typename TA, int TRI>
 __global__ __launch_bounds__(TRT) void k_trgemv(int n, const TA* __restrict__ T, int ldt,
@@ -217,27 +218,29 @@ __global__ __launch_bounds__(TRT) void k_trgemv(int n, const TA* __restrict__ T,
   int j0 = s * chunk, j1 = min(n, j0 + chunk);
   if (TRI == 1) j1 = min(j1, rhi);       // lower: columns j <= i
   if (TRI == 2) j0 = max(j0, rlo);       // upper: columns j >= i
+  // gathered, scaled slice of the input vector, once per workgroup
+  __shared__ double sx[kTrChunk];
+  for (int t = threadIdx.x; t < j1 - j0; t += TRT) {
+    const int j = j0 + t;
+    double v;
+    if (perm) { const int q = perm[j]; v = R ? R[q] * x[q] : x[q]; } else v = x[j];
+    sx[t] = v;
+  }
+  __syncthreads();
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   if (i < n) {
+    const double* xs = sx - j0;
     int j = j0;
     const TA* a = T + (size_t)j0 * ldt + i;
     for (; j + 3 < j1; j += 4) {
-      double x0, x1, x2, x3;
-      if (perm) {
-        const int q0 = perm[j], q1 = perm[j + 1], q2 = perm[j + 2], q3 = perm[j + 3];
-        x0 = R ? R[q0] * x[q0] : x[q0]; x1 = R ? R[q1] * x[q1] : x[q1];
-        x2 = R ? R[q2] * x[q2] : x[q2]; x3 = R ? R[q3] * x[q3] : x[q3];
-      } else { x0 = x[j]; x1 = x[j + 1]; x2 = x[j + 2]; x3 = x[j + 3]; }
-      acc0 = __fma_rn((double)a[0], x0, acc0);
-      acc1 = __fma_rn((double)a[ldt], x1, acc1);
-      acc2 = __fma_rn((double)a[2 * (size_t)ldt], x2, acc2);
-      acc3 = __fma_rn((double)a[3 * (size_t)ldt], x3, acc3);
+      acc0 = __fma_rn((double)a[0], xs[j], acc0);
+      acc1 = __fma_rn((double)a[ldt], xs[j + 1], acc1);
+      acc2 = __fma_rn((double)a[2 * (size_t)ldt], xs[j + 2], acc2);
+      acc3 = __fma_rn((double)a[3 * (size_t)ldt], xs[j + 3], acc3);
       a += 4 * (size_t)ldt;
     }
     for (; j < j1; ++j) {
-      double x0;
-      if (perm) { const int q0 = perm[j]; x0 = R ? R[q0] * x[q0] : x[q0]; } else x0 = x[j];
-      acc0 = __fma_rn((double)a[0], x0, acc0);
+      acc0 = __fma_rn((double)a[0], xs[j], acc0);
       a += ldt;
     }
     part[(size_t)s * n + i] = __dadd_rn(__dadd_rn(acc0, acc1), __dadd_rn(acc2, acc3));
@@ -266,6 +269,8 @@ int trgemv(Ctx& c, int n, int store_prec, const void* T, int tri, const double* 
   int ns = (1024 + rb - 1) / rb;
   const int maxs = (n + 31) / 32;
   if (ns > maxs) ns = maxs;
+  const int mins = (n + kTrChunk - 1) / kTrChunk;
+  if (ns < mins) ns = mins;
   if (ns < 1) ns = 1;
   const int chunk = (n + ns - 1) / ns;
   double* part = (double*)c.grow(c.tr_part, (size_t)ns * n * sizeof(double));

@@ -47,3 +47,13 @@ def test_host_only_calls():
     assert M.nb_auto(4096, "fp64") == 8
     assert M.lib().msir_status_string(0) == b"converged"
     assert M.workspace_bytes(1000) > 8 * 1000 * 1000
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libmsir.so not built")
+def test_panel_width_rule_agrees_with_oracle():
+    # the oracle and the library state the same default panel-width rule independently
+    from paper_2107_06200_amd import msir as M
+    from oracle import lu as OLU
+    for n in (1, 64, 100, 1024, 1025, 2048, 3000, 4096, 5000, 8192):
+        for fmt in ("fp16", "bf16", "fp32", "fp64"):
+            assert M.nb_auto(n, fmt) == OLU.nb_auto(n, fmt), (n, fmt)
