@@ -127,6 +127,8 @@ typedef struct msir_handle msir_handle;
 #define MSIR_ERR_HIP       -100
 #define MSIR_ERR_ALLOC     -101
 #define MSIR_ERR_SIZE      -102   /* n outside [1, MSIR_MAX_N]                     */
+#define MSIR_ERR_TIMEOUT   -103   /* a substitution launch's bounded wait expired;
+                                     its results are invalid                      */
 #define MSIR_MAX_N         8192   /* register-resident panel limit (see msir_nb_auto) */
 
 /* Create a handle on HIP device `device`.  `stream` is a hipStream_t (NULL: the
@@ -252,8 +254,9 @@ typedef enum {
     MSIR_T_MATVEC = 4,   /* A v inside GMRES                                     */
     MSIR_T_RESID = 5,    /* residual b - A x and its scaling                     */
     MSIR_T_ARNOLDI = 6,  /* modified Gram-Schmidt + Givens                       */
-    MSIR_T_OTHER = 7,
-    MSIR_T_COUNT = 8
+    MSIR_T_TRGEMV = 7,   /* M^{-1} v through the explicit triangular inverses    */
+    MSIR_T_OTHER = 8,
+    MSIR_T_COUNT = 9
 } msir_timer;
 /* enable != 0: start timing (counters reset); 0: stop.                          */
 MSIR_API int msir_timing(msir_handle* h, int enable);

@@ -136,73 +136,6 @@ __device__ __forceinline__ bool arrive_last(unsigned* counter) {
   return last;
 }
 
-// ------------------------------------------------------------------ GEMV partials
-// y_part[split][i] = sum_{j in split} A[i, j] x[j] (TA: double or float matrix).
-// MODE 0: float64 fused multiply-add accumulation into part_hi.
-// MODE 1: double-double accumulation (exact products) into part_hi/part_lo.
-// MODE 2: both in one pass over A: float64 into part_x, double-double into hi/lo.
-template <typename TA, int MODE>
-__global__ __launch_bounds__(RT) void k_gemv_part(int n, const TA* __restrict__ A, int lda,
-                                                  const double* __restrict__ x, int chunk,
-                                                  double* __restrict__ part_hi, double* __restrict__ part_lo,
-                                                  double* __restrict__ part_x, const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int i = blockIdx.x * RT + threadIdx.x;
-  const int s = blockIdx.y;
-  const int j0 = s * chunk;
-  const int j1 = min(n, j0 + chunk);
-  // this workgroup's slice of x, read once into LDS (avoids a dependent global
-  // load per column in the inner loop)
-  __shared__ double sx[kMaxChunk];
-  for (int t = threadIdx.x; t < j1 - j0; t += RT) sx[t] = x[j0 + t];
-  __syncthreads();
-  x = sx - j0;
-  if (i >= n) return;
-  const TA* a = A + (size_t)j0 * lda + i;
-  if (MODE == 0) {
-    double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-    int j = j0;
-    for (; j + 3 < j1; j += 4) {
-      const double a0 = (double)a[0], a1 = (double)a[lda], a2 = (double)a[2 * (size_t)lda],
-                   a3 = (double)a[3 * (size_t)lda];
-      acc0 = __fma_rn(a0, x[j], acc0);
-      acc1 = __fma_rn(a1, x[j + 1], acc1);
-      acc2 = __fma_rn(a2, x[j + 2], acc2);
-      acc3 = __fma_rn(a3, x[j + 3], acc3);
-      a += 4 * (size_t)lda;
-    }
-    for (; j < j1; ++j) {
-      acc0 = __fma_rn((double)a[0], x[j], acc0);
-      a += lda;
-    }
-    part_hi[(size_t)s * n + i] = __dadd_rn(__dadd_rn(acc0, acc1), __dadd_rn(acc2, acc3));
-  } else {
-    double h = 0.0, l = 0.0, f = 0.0;
-    int j = j0;
-    for (; j + 1 < j1; j += 2) {
-      const double a0 = (double)a[0], a1 = (double)a[lda];
-      double p, e;
-      two_prod(a0, x[j], p, e);
-      dd_add(h, l, p, e, h, l);
-      two_prod(a1, x[j + 1], p, e);
-      dd_add(h, l, p, e, h, l);
-      if (MODE == 2) { f = __fma_rn(a0, x[j], f); f = __fma_rn(a1, x[j + 1], f); }
-      a += 2 * (size_t)lda;
-    }
-    for (; j < j1; ++j) {
-      const double a0 = (double)a[0];
-      double p, e;
-      two_prod(a0, x[j], p, e);
-      dd_add(h, l, p, e, h, l);
-      if (MODE == 2) f = __fma_rn(a0, x[j], f);
-      a += lda;
-    }
-    part_hi[(size_t)s * n + i] = h;
-    part_lo[(size_t)s * n + i] = l;
-    if (MODE == 2) part_x[(size_t)s * n + i] = f;
-  }
-}
-
 // Combine partials: r = b - sum.  MODE as above.  Writes r (r_hi[, r_lo]) and
 // per-block maxima; the last block folds them into s_out[0] = ||r||_inf of the
 // residual in u_r and s_out[1] = ||r||_inf of the double-double residual (MODE 1, 2),
@@ -219,23 +152,21 @@ __global__ __launch_bounds__(RT) void k_resid_finish(int n, int nsplit, const do
   int nan = 0;
   if (i < n) {
     if (MODE == 0) {
-      double acc = 0.0;
-      for (int s = 0; s < nsplit; ++s) acc = __dadd_rn(acc, part_hi[(size_t)s * n + i]);
+      const double acc = fold_sum(part_hi + i, (size_t)n, 0, nsplit);
       const double r = __dsub_rn(b[i], acc);
       r_hi[i] = r;
       m = fabs(r);
       mt = m;
     } else {
       double h = b[i], l = 0.0;
-      for (int s = 0; s < nsplit; ++s) dd_add(h, l, -part_hi[(size_t)s * n + i], -part_lo[(size_t)s * n + i], h, l);
+      fold_dd(part_hi + i, part_lo + i, (size_t)n, 0, nsplit, -1.0, h, l);
       mt = fabs(__dadd_rn(h, l));
       if (MODE == 1) {
         r_hi[i] = h;
         r_lo[i] = l;
         m = mt;
       } else {
-        double acc = 0.0;
-        for (int s = 0; s < nsplit; ++s) acc = __dadd_rn(acc, part_x[(size_t)s * n + i]);
+        const double acc = fold_sum(part_x + i, (size_t)n, 0, nsplit);
         const double r = __dsub_rn(b[i], acc);
         r_hi[i] = r;
         m = fabs(r);
@@ -297,8 +228,8 @@ static int nsplit_for(int n) {
 
 int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
              double* rhat, double* s_dev, bool want_true) {
-  const int ns = nsplit_for(n);
-  const int chunk = (n + ns - 1) / ns;
+  const GemvPlan g = gemv_plan(n, 0);
+  const int ns = g.ns;
   const int rb = (n + RT - 1) / RT;
   double* ph = c.ws_part_hi(ns * (size_t)n);
   double* pl = c.ws_part_lo(ns * (size_t)n);
@@ -306,68 +237,36 @@ int residual(Ctx& c, int n, const double* A, int lda, const double* x, const dou
   double* rh = c.ws_r_hi(n);
   double* rl = c.ws_r_lo(n);
   if (!ph || !pl || !px || !rh || !rl) return MSIR_ERR_ALLOC;
-  dim3 g(rb, ns);
-  const int _slot = c.tbegin(5);
-  if (ur == P_DD) {
-    k_gemv_part<double, 1><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, nullptr, nullptr);
+  const int mode = (ur == P_DD) ? 1 : (want_true ? 2 : 0);
+  const int _slot = c.tbegin(MSIR_T_RESID);
+  int rc = gemv_partials(c, g, n, P_FP64, A, lda, x, nullptr, nullptr, mode, ph, pl, px, nullptr);
+  if (rc) return rc;
+  if (mode == 1)
     k_resid_finish<1><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
-  } else if (want_true) {
-    k_gemv_part<double, 2><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, px, nullptr);
+  else if (mode == 2)
     k_resid_finish<2><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, px, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
-  } else {
-    k_gemv_part<double, 0><<<g, RT, 0, c.stream>>>(n, A, lda, x, chunk, ph, pl, nullptr, nullptr);
+  else
     k_resid_finish<0><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
-  }
   c.tend(_slot);
   HIP_CHECK(hipGetLastError());
   return 0;
 }
 
 // ------------------------------------------------------------------ A v in precision p
-template <bool DD>
-__global__ __launch_bounds__(RT) void k_matvec_finish(int n, int nsplit, const double* __restrict__ part_hi,
-                                                      const double* __restrict__ part_lo, int p,
-                                                      double* __restrict__ y_hi, double* __restrict__ y_lo,
-                                                      const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int i = blockIdx.x * RT + threadIdx.x;
-  if (i >= n) return;
-  if (!DD) {
-    double acc = 0.0;
-    for (int s = 0; s < nsplit; ++s) acc = __dadd_rn(acc, part_hi[(size_t)s * n + i]);
-    y_hi[i] = round_to(acc, p);
-  } else {
-    double h = 0.0, l = 0.0;
-    for (int s = 0; s < nsplit; ++s) dd_add(h, l, part_hi[(size_t)s * n + i], part_lo[(size_t)s * n + i], h, l);
-    y_hi[i] = h;
-    y_lo[i] = l;
-  }
-}
-
 // y = A v with p in {FP32 (Au = fp32 copy of A), FP64, DD}; v holds values in u (float64 array).
 int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
            double* y_hi, double* y_lo, const int* skip) {
-  const int ns = nsplit_for(n);
-  const int chunk = (n + ns - 1) / ns;
-  const int rb = (n + RT - 1) / RT;
-  double* ph = c.ws_part_hi(ns * (size_t)n);
-  double* pl = c.ws_part_lo(ns * (size_t)n);
+  const GemvPlan g = gemv_plan(n, 0);
+  double* ph = c.ws_part_hi(g.ns * (size_t)n);
+  double* pl = c.ws_part_lo(g.ns * (size_t)n);
   if (!ph || !pl) return MSIR_ERR_ALLOC;
-  dim3 g(rb, ns);
-  const int _slot = c.tbegin(4);
-  if (p == P_FP32) {
-    k_gemv_part<float, 0><<<g, RT, 0, c.stream>>>(n, Au, ldau, v, chunk, ph, pl, nullptr, skip);
-    k_matvec_finish<false><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_FP32, y_hi, y_lo, skip);
-  } else if (p == P_FP64) {
-    k_gemv_part<double, 0><<<g, RT, 0, c.stream>>>(n, A, lda, v, chunk, ph, pl, nullptr, skip);
-    k_matvec_finish<false><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_FP64, y_hi, y_lo, skip);
-  } else {
-    k_gemv_part<double, 1><<<g, RT, 0, c.stream>>>(n, A, lda, v, chunk, ph, pl, nullptr, skip);
-    k_matvec_finish<true><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, P_DD, y_hi, y_lo, skip);
-  }
+  const int _slot = c.tbegin(MSIR_T_MATVEC);
+  int rc;
+  if (p == P_FP32) rc = gemv_partials(c, g, n, P_FP32, Au, ldau, v, nullptr, nullptr, 0, ph, pl, nullptr, skip);
+  else rc = gemv_partials(c, g, n, P_FP64, A, lda, v, nullptr, nullptr, p == P_DD ? 1 : 0, ph, pl, nullptr, skip);
+  if (!rc) rc = gemv_finish(c, g, n, ph, pl, 1.0, nullptr, p, y_hi, y_lo, skip);
   c.tend(_slot);
-  HIP_CHECK(hipGetLastError());
-  return 0;
+  return rc;
 }
 
 // ------------------------------------------------------------------ norms of A and b
@@ -389,7 +288,7 @@ __global__ __launch_bounds__(RT) void k_norms_finish(int n, int ns, const double
   const int i = blockIdx.x * RT + threadIdx.x;
   double ra = 0.0, bb = 0.0;
   if (i < n) {
-    for (int s = 0; s < ns; ++s) ra = __dadd_rn(ra, part[(size_t)s * n + i]);
+    ra = fold_sum(part + i, (size_t)n, 0, ns);
     if (b) bb = fabs(b[i]);
   }
   __shared__ double sh[2][RT / 64];
@@ -449,7 +348,7 @@ __global__ __launch_bounds__(RT) void k_errors_finish(int n, int ns, const doubl
   double rm = 0.0, cb = 0.0;
   if (i < n) {
     double den = 0.0;
-    for (int s = 0; s < ns; ++s) den = __dadd_rn(den, den_part[(size_t)s * n + i]);
+    den = fold_sum(den_part + i, (size_t)n, 0, ns);
     den = __dadd_rn(den, fabs(b[i]));
     double r = fabs(__dadd_rn(r_hi[i], r_lo[i]));
     rm = r;

@@ -175,6 +175,68 @@ __device__ __forceinline__ int wave_or(int v) {
   return v;
 }
 
+// Wave sum through DPP lane moves (no LDS traffic): pairs, quads, half rows,
+// rows, then rows 0+1 / 2+3 (row_bcast15) and all four rows (row_bcast31).  The
+// total ends in lane 63 and is returned to every lane.  Fixed order, so the
+// result is the same on every run.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = __dadd_rn(v, dpp_d<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
+  v = __dadd_rn(v, dpp_d<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
+  v = __dadd_rn(v, dpp_d<0x141, 0xF>(v));   // row_half_mirror
+  v = __dadd_rn(v, dpp_d<0x140, 0xF>(v));   // row_mirror
+  v = __dadd_rn(v, dpp_d<0x142, 0xA>(v));   // row_bcast15 into rows 1, 3
+  v = __dadd_rn(v, dpp_d<0x143, 0xC>(v));   // row_bcast31 into rows 2, 3
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Round to format U (compile-time), returned as float64.
+template <int U>
+__device__ __forceinline__ double round_c(double x) {
+  if constexpr (U == P_FP16) return (double)f16_bits_to_f32(f64_to_f16_bits(x));
+  else if constexpr (U == P_BF16) return (double)bf16_bits_to_f32(f64_to_bf16_bits(x));
+  else if constexpr (U == P_FP32) return (double)(float)x;
+  else return x;
+}
+
+// Ordered folds of strided partial sums p[s * stride] for s in [s_lo, s_hi): the
+// loads are issued sixteen at a time, the additions stay in slice order.
+__device__ __forceinline__ double fold_sum(const double* __restrict__ p, size_t stride, int s_lo, int s_hi) {
+  double t = 0.0;
+  int s = s_lo;
+  for (; s + 16 <= s_hi; s += 16) {
+    double q[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) q[k] = p[(size_t)(s + k) * stride];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) t = __dadd_rn(t, q[k]);
+  }
+  for (; s < s_hi; ++s) t = __dadd_rn(t, p[(size_t)s * stride]);
+  return t;
+}
+// (h, l) += sum of sign * (ph[s], pl[s]) in double-double, slice order
+__device__ __forceinline__ void fold_dd(const double* __restrict__ ph, const double* __restrict__ pl, size_t stride,
+                                        int s_lo, int s_hi, double sign, double& h, double& l) {
+  int s = s_lo;
+  for (; s + 8 <= s_hi; s += 8) {
+    double qh[8], ql[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) { qh[k] = ph[(size_t)(s + k) * stride]; ql[k] = pl[(size_t)(s + k) * stride]; }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) dd_add(h, l, sign * qh[k], sign * ql[k], h, l);
+  }
+  for (; s < s_hi; ++s) dd_add(h, l, sign * ph[(size_t)s * stride], sign * pl[(size_t)s * stride], h, l);
+}
+
 // Block-wide sum of a double over blockDim.x threads (multiple of 64), deterministic order.
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sh) {

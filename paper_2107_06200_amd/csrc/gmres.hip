@@ -20,7 +20,6 @@
 namespace msir {
 
 constexpr int GNT = 1024;
-constexpr int GPT = MSIR_MAX_N / GNT;  // values per thread
 
 // beta = ||resid||_2; g[0] = beta; V0 = fl_u(resid / beta); status reset
 __global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __restrict__ resid, double* __restrict__ V0,
@@ -41,56 +40,81 @@ __global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __rest
   }
 }
 
+// One modified Gram-Schmidt step against basis vector i held in B: h = <B, w> (one
+// barrier), w <- fl_u(w - h B); then B is refilled with v_{i+4} (if i + 4 <= j), so
+// four basis vectors are in flight while the inner products are reduced.
+template <int G, int U>
+__device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], double (&B)[G],
+                                         const double* __restrict__ V, int ldv, double* __restrict__ H, int ldh,
+                                         double (*sh)[GNT / 64]) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  double acc = 0.0;
+#pragma unroll
+  for (int t = 0; t < G; ++t) acc = __fma_rn(B[t], w[t], acc);
+  acc = wave_sum_dpp(acc);
+  if (lane == 0) sh[i & 1][wv] = acc;
+  __syncthreads();
+  double h = 0.0;
+#pragma unroll
+  for (int q = 0; q < GNT / 64; ++q) h = __dadd_rn(h, sh[i & 1][q]);
+#pragma unroll
+  for (int t = 0; t < G; ++t) {
+    const int r = tid + t * GNT;
+    if (r < n) w[t] = round_c<U>(__dsub_rn(w[t], __dmul_rn(h, B[t])));
+  }
+  if (tid == 0) H[(size_t)j * ldh + i] = h;
+  if (i + 4 <= j) {
+    const double* vp = V + (size_t)(i + 4) * ldv;
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const int r = tid + t * GNT;
+      B[t] = r < n ? vp[r] : 0.0;
+    }
+  }
+}
+
+// Arnoldi step j: w (= M^{-1} A v_j, in u) is orthogonalised against v_0..v_j by
+// modified Gram-Schmidt, h_{j+1,j} = ||w||_2, the new Hessenberg column is rotated
+// by the previous Givens rotations and a new rotation zeroes h_{j+1,j}; g is
+// rotated and the stopping test |g_{j+1}| <= tau beta0 is taken.  G values per
+// thread (n <= G * GNT), U the working precision.
+template <int G, int U>
 __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restrict__ V, int ldv,
                                                  const double* __restrict__ w_in, double* __restrict__ H, int ldh,
                                                  double* __restrict__ cs, double* __restrict__ sn,
                                                  double* __restrict__ g, const double* __restrict__ beta0, double tau,
-                                                 int u, GStatus* st) {
+                                                 GStatus* st) {
   if (st->done) return;
-  // partial sums of each wave, double-buffered by the parity of the dot index so that
-  // one barrier per inner product suffices
+  // per-wave partial sums, double-buffered by the parity of the inner-product index
+  // so that one barrier per inner product suffices
   __shared__ double sh[2][GNT / 64];
-  __shared__ double s_hn;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  double w[GPT], v[GPT];
+  double w[G], b0[G], b1[G], b2[G], b3[G];
 #pragma unroll
-  for (int t = 0; t < GPT; ++t) {
+  for (int t = 0; t < G; ++t) {
     const int r = tid + t * GNT;
-    w[t] = r < n ? w_in[r] : 0.0;
-    v[t] = r < n ? V[r] : 0.0;
+    const bool in = r < n;
+    w[t] = in ? w_in[r] : 0.0;
+    b0[t] = in ? V[r] : 0.0;
+    b1[t] = (in && j >= 1) ? V[(size_t)ldv + r] : 0.0;
+    b2[t] = (in && j >= 2) ? V[2 * (size_t)ldv + r] : 0.0;
+    b3[t] = (in && j >= 3) ? V[3 * (size_t)ldv + r] : 0.0;
   }
-  for (int i = 0; i <= j; ++i) {
-    // next basis vector in flight while this inner product is reduced
-    double vn[GPT];
-    const double* vnp = V + (size_t)(i + 1) * ldv;
-#pragma unroll
-    for (int t = 0; t < GPT; ++t) {
-      const int r = tid + t * GNT;
-      vn[t] = (i < j && r < n) ? vnp[r] : 0.0;
-    }
-    double acc = 0.0;
-#pragma unroll
-    for (int t = 0; t < GPT; ++t) acc = __fma_rn(v[t], w[t], acc);
-    acc = wave_sum(acc);
-    if (lane == 0) sh[i & 1][wv] = acc;
-    __syncthreads();
-    double h = 0.0;
-#pragma unroll
-    for (int q = 0; q < GNT / 64; ++q) h = __dadd_rn(h, sh[i & 1][q]);
-#pragma unroll
-    for (int t = 0; t < GPT; ++t) {
-      const int r = tid + t * GNT;
-      if (r < n) w[t] = round_to(__dsub_rn(w[t], __dmul_rn(h, v[t])), u);
-    }
-    if (tid == 0) H[(size_t)j * ldh + i] = h;
-#pragma unroll
-    for (int t = 0; t < GPT; ++t) v[t] = vn[t];
+  for (int i = 0; i <= j; i += 4) {
+    mgs_step<G, U>(n, i, j, w, b0, V, ldv, H, ldh, sh);
+    if (i + 1 > j) break;
+    mgs_step<G, U>(n, i + 1, j, w, b1, V, ldv, H, ldh, sh);
+    if (i + 2 > j) break;
+    mgs_step<G, U>(n, i + 2, j, w, b2, V, ldv, H, ldh, sh);
+    if (i + 3 > j) break;
+    mgs_step<G, U>(n, i + 3, j, w, b3, V, ldv, H, ldh, sh);
   }
   double acc = 0.0;
 #pragma unroll
-  for (int t = 0; t < GPT; ++t) acc = __fma_rn(w[t], w[t], acc);
-  acc = wave_sum(acc);
+  for (int t = 0; t < G; ++t) acc = __fma_rn(w[t], w[t], acc);
+  acc = wave_sum_dpp(acc);
   const int pb = (j + 1) & 1;
   if (lane == 0) sh[pb][wv] = acc;
   __syncthreads();
@@ -123,10 +147,29 @@ __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restric
   }
   double* vnx = V + (size_t)(j + 1) * ldv;
 #pragma unroll
-  for (int t = 0; t < GPT; ++t) {
+  for (int t = 0; t < G; ++t) {
     const int r = tid + t * GNT;
-    if (r < n) vnx[r] = round_to(w[t] / hn, u);
+    if (r < n) vnx[r] = round_c<U>(w[t] / hn);
   }
+}
+
+template <int G>
+static void launch_arnoldi_g(hipStream_t s, int n, int j, double* V, int ldv, const double* w, double* H, int ldh,
+                             double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
+  switch (u) {
+    case P_FP16: k_arnoldi<G, P_FP16><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    case P_BF16: k_arnoldi<G, P_BF16><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    case P_FP32: k_arnoldi<G, P_FP32><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    default: k_arnoldi<G, P_FP64><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+  }
+}
+
+static void launch_arnoldi(hipStream_t s, int n, int j, double* V, int ldv, const double* w, double* H, int ldh,
+                           double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
+  if (n <= GNT) launch_arnoldi_g<1>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else if (n <= 2 * GNT) launch_arnoldi_g<2>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else if (n <= 4 * GNT) launch_arnoldi_g<4>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else launch_arnoldi_g<8>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
 }
 
 // y = R^{-1} g (upper triangular from the rotated Hessenberg), one wave,
@@ -209,8 +252,8 @@ int gmres(Ctx& c, GmresWork& gw, const GmresOp& op, const double* rhat, double t
     for (int it = 0; it < m; ++it) {
       rc = op.apply_full(c, gw.V + (size_t)it * ldv, gw.w, &st->done);
       if (rc) return rc;
-      MSIR_TIMED(c, 6, (k_arnoldi<<<1, GNT, 0, c.stream>>>(n, it, gw.V, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g,
-                                                          gw.beta0, tau, u, st)));
+      MSIR_TIMED(c, MSIR_T_ARNOLDI, launch_arnoldi(c.stream, n, it, gw.V, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g,
+                                                   gw.beta0, tau, u, st));
       HIP_CHECK(hipGetLastError());
       if ((it + 1) % CHK == 0 || it + 1 == m) {
         HIP_CHECK(hipMemcpyAsync(gw.host_status, st, sizeof(GStatus), hipMemcpyDeviceToHost, c.stream));

@@ -196,98 +196,19 @@ int square_to_f32(Ctx& c, int n, const double* X, float* Xf) {
 }
 
 // ------------------------------------------------------------------ triangular GEMV
-// y = round_p(oscale_i * sum_j T_ij xin_j) with T lower (TRI=1) or upper (TRI=2)
-// triangular, column-major, storage TA; xin_j = (perm ? R[perm[j]] x[perm[j]] : x[j]);
-// oscale_i = mu * S[i] (or 1).  Column range split over blockIdx.y; the last
-// workgroup of each 256-row block (per-block counter) sums the partials in split
-// order, so results are reproducible.
-constexpr int TRT = 256;
-constexpr int kTrChunk = 512;
-
-template <typename TA, int TRI>
-__global__ __launch_bounds__(TRT) void k_trgemv(int n, const TA* __restrict__ T, int ldt,
-                                                const double* __restrict__ x, const int* __restrict__ perm,
-                                                const double* __restrict__ R, double mu, const double* __restrict__ S,
-                                                int p, int chunk, double* __restrict__ part,
-                                                unsigned* __restrict__ counters, double* __restrict__ y,
-                                                const int* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int rb = blockIdx.x, s = blockIdx.y;
-  const int i = rb * TRT + threadIdx.x;
-  const int rlo = rb * TRT, rhi = min(n, rlo + TRT);
-  int j0 = s * chunk, j1 = min(n, j0 + chunk);
-  if (TRI == 1) j1 = min(j1, rhi);       // lower: columns j <= i
-  if (TRI == 2) j0 = max(j0, rlo);       // upper: columns j >= i
-  // gathered, scaled slice of the input vector, once per workgroup
-  __shared__ double sx[kTrChunk];
-  for (int t = threadIdx.x; t < j1 - j0; t += TRT) {
-    const int j = j0 + t;
-    double v;
-    if (perm) { const int q = perm[j]; v = R ? R[q] * x[q] : x[q]; } else v = x[j];
-    sx[t] = v;
-  }
-  __syncthreads();
-  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-  if (i < n) {
-    const double* xs = sx - j0;
-    int j = j0;
-    const TA* a = T + (size_t)j0 * ldt + i;
-    for (; j + 3 < j1; j += 4) {
-      acc0 = __fma_rn((double)a[0], xs[j], acc0);
-      acc1 = __fma_rn((double)a[ldt], xs[j + 1], acc1);
-      acc2 = __fma_rn((double)a[2 * (size_t)ldt], xs[j + 2], acc2);
-      acc3 = __fma_rn((double)a[3 * (size_t)ldt], xs[j + 3], acc3);
-      a += 4 * (size_t)ldt;
-    }
-    for (; j < j1; ++j) {
-      acc0 = __fma_rn((double)a[0], xs[j], acc0);
-      a += ldt;
-    }
-    part[(size_t)s * n + i] = __dadd_rn(__dadd_rn(acc0, acc1), __dadd_rn(acc2, acc3));
-  }
-  // last workgroup of this row block folds the partials
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = (atomicAdd(&counters[rb], 1u) == gridDim.y - 1);
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  if (i < n) {
-    double t = 0.0;
-    for (int q = 0; q < (int)gridDim.y; ++q)
-      t = __dadd_rn(t, __hip_atomic_load(&part[(size_t)q * n + i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    if (S) t = mu * (S[i] * t);
-    y[i] = round_to(t, p);
-  }
-  if (threadIdx.x == 0) counters[rb] = 0u;
-}
-
+// y = round_p(oscale_i * sum_j T_ij xin_j), T lower (tri 1) or upper (tri 2), n x n
+// column-major with ld n, storage FP32 or FP64; only the triangle is read.
 int trgemv(Ctx& c, int n, int store_prec, const void* T, int tri, const double* x, const int* perm, const double* R,
            double mu, const double* S, int p, double* y, const int* skip) {
-  const int rb = (n + TRT - 1) / TRT;
-  int ns = (1024 + rb - 1) / rb;
-  const int maxs = (n + 31) / 32;
-  if (ns > maxs) ns = maxs;
-  const int mins = (n + kTrChunk - 1) / kTrChunk;
-  if (ns < mins) ns = mins;
-  if (ns < 1) ns = 1;
-  const int chunk = (n + ns - 1) / ns;
-  double* part = (double*)c.grow(c.tr_part, (size_t)ns * n * sizeof(double));
-  unsigned* cnt = (unsigned*)c.grow(c.tr_cnt, (size_t)(rb + 4) * sizeof(unsigned));
-  if (!part || !cnt) return MSIR_ERR_ALLOC;
-  dim3 g(rb, ns);
-  const int slot = c.tbegin(3);
-  if (store_prec == P_FP32) {
-    if (tri == 1) k_trgemv<float, 1><<<g, TRT, 0, c.stream>>>(n, (const float*)T, n, x, perm, R, mu, S, p, chunk, part, cnt, y, skip);
-    else k_trgemv<float, 2><<<g, TRT, 0, c.stream>>>(n, (const float*)T, n, x, perm, R, mu, S, p, chunk, part, cnt, y, skip);
-  } else {
-    if (tri == 1) k_trgemv<double, 1><<<g, TRT, 0, c.stream>>>(n, (const double*)T, n, x, perm, R, mu, S, p, chunk, part, cnt, y, skip);
-    else k_trgemv<double, 2><<<g, TRT, 0, c.stream>>>(n, (const double*)T, n, x, perm, R, mu, S, p, chunk, part, cnt, y, skip);
-  }
+  if (tri != 1 && tri != 2) return -3;
+  const GemvPlan g = gemv_plan(n, tri);
+  double* part = (double*)c.grow(c.tr_part, (size_t)g.ns * n * sizeof(double));
+  if (!part) return MSIR_ERR_ALLOC;
+  const int slot = c.tbegin(MSIR_T_TRGEMV);
+  int rc = gemv_partials(c, g, n, store_prec, T, n, x, perm, R, 0, part, nullptr, nullptr, skip);
+  if (!rc) rc = gemv_finish(c, g, n, part, nullptr, mu, S, p, y, nullptr, skip);
   c.tend(slot);
-  HIP_CHECK(hipGetLastError());
-  return 0;
+  return rc;
 }
 
 }  // namespace msir

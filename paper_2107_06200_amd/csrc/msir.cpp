@@ -375,6 +375,7 @@ const char* msir_status_string(int s) {
     case MSIR_NOT_CONVERGED: return "not converged (precision ladder exhausted or step cap reached)";
     case MSIR_SINGULAR: return "singular factor at the highest precision";
     case MSIR_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
+    case MSIR_ERR_TIMEOUT: return "a substitution launch's bounded wait expired";
     case MSIR_ERR_ALLOC: return "device memory could not be allocated within the handle budget";
     case MSIR_ERR_SIZE: return "n outside [1, 8192]";
   }
@@ -590,8 +591,10 @@ int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, cons
   a.y_hi = dy; a.y_lo = (comp == MSIR_DD) ? dy + n : nullptr; a.out_round = -1; a.skip = nullptr; a.dinv = nullptr;
   rc = trsv(h->c, a);
   if (rc) return rc;
-  HIP_CHECK(hipStreamSynchronize(h->c.stream));
-  return 0;
+  unsigned terr = 0;
+  rc = trsv_check(h->c, &terr);
+  if (rc) return rc;
+  return terr ? MSIR_ERR_TIMEOUT : 0;
 }
 
 int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double* dx, const double* db,
@@ -703,6 +706,10 @@ int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, co
   rc = gmres(h->c, h->gw, op, drhat, tau, k_max, restart, dd, &kk);
   if (rc) return rc;
   HIP_CHECK(hipStreamSynchronize(h->c.stream));
+  unsigned terr = 0;
+  rc = trsv_check(h->c, &terr);
+  if (rc) return rc;
+  if (terr) return MSIR_ERR_TIMEOUT;
   if (k) *k = kk;
   return 0;
 }
@@ -733,6 +740,11 @@ int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* d
   HIP_CHECK(hipSetDevice(h->c.device));
   std::vector<msir_step> H;
   int rc = solve_one(h, n, dA, lda, db, dx, dxt, P, out, H);
+  unsigned terr = 0;
+  if (rc >= 0 && trsv_check(h->c, &terr) == 0 && terr) {
+    msir_set_error("substitution wait expired", __FILE__, __LINE__);
+    rc = MSIR_ERR_TIMEOUT;
+  }
   if (hist_len) *hist_len = (int)H.size();
   if (hist && hist_cap > 0) memcpy(hist, H.data(), std::min((size_t)hist_cap, H.size()) * sizeof(msir_step));
   return rc;
@@ -1047,7 +1059,7 @@ int msir_timing(msir_handle* h, int enable) {
     for (int i = 0; i < c.ev_cap; ++i) HIP_CHECK(hipEventCreate(&c.ev_pool[i]));
   }
   c.tflush();
-  for (int i = 0; i < 8; ++i) { c.t_ms[i] = 0.0; c.t_launch[i] = 0; }
+  for (int i = 0; i < MSIR_T_COUNT; ++i) { c.t_ms[i] = 0.0; c.t_launch[i] = 0; }
   c.timing = enable != 0;
   return 0;
 }

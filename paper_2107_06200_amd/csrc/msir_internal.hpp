@@ -47,8 +47,8 @@ struct Ctx {
   hipEvent_t* ev_pool = nullptr;
   int ev_cap = 0, ev_used = 0;
   int* ev_cls = nullptr;
-  long long t_launch[8] = {0};
-  double t_ms[8] = {0};
+  long long t_launch[MSIR_T_COUNT] = {0};
+  double t_ms[MSIR_T_COUNT] = {0};
   int tbegin(int cls);           // returns a slot or -1
   void tend(int slot);
   void tflush();                 // fold recorded events into the totals
@@ -112,6 +112,7 @@ struct TrsvArgs {
   const double* dinv;  // inverted diagonal blocks (mode 1)
 };
 int trsv(Ctx& c, const TrsvArgs& a);
+int trsv_check(Ctx& c, unsigned* out);
 
 // Explicit inverses X = L^{-1}, Y = U^{-1} (float64, n x n, column-major, ld n) of the
 // factors stored in W; T: 64 x n float64 scratch; dinv: (n/64 + 1) * 64 * 64 float64.
@@ -122,6 +123,22 @@ int square_to_f32(Ctx& c, int n, const double* X, float* Xf);
 // null); oscale_i = S ? mu S[i] : 1.
 int trgemv(Ctx& c, int n, int store_prec, const void* T, int tri, const double* x, const int* perm, const double* R,
            double mu, const double* S, int p, double* y, const int* skip);
+// Streaming GEMV: partial sums per (256-row block, column slice), then an ordered fold.
+// tri: 0 full, 1 lower, 2 upper triangular operand (zeros outside the triangle are not read).
+struct GemvPlan {
+  int tri = 0;
+  int rb = 1;      // row blocks
+  int ns = 1;      // column slices
+  int chunk = 1;   // columns per slice
+};
+GemvPlan gemv_plan(int n, int tri);
+// a_prec FP32 (mode 0 only) or FP64; mode 0 float64 sums into ph, 1 double-double into
+// ph/pl, 2 both (double-double into ph/pl, float64 into px).  Buffers hold ns * n doubles.
+int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const double* x,
+                  const int* perm, const double* R, int mode, double* ph, double* pl, double* px, const int* skip);
+// y = round_p(oscale * folded partials), oscale_i = S ? mu S[i] : 1; p == DD writes y_hi/y_lo.
+int gemv_finish(Ctx& c, const GemvPlan& g, int n, const double* ph, const double* pl, double mu, const double* S,
+                int p, double* y_hi, double* y_lo, const int* skip);
 int diag_block_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* dinv);
 size_t diag_inv_doubles(int n);
 

@@ -8,17 +8,23 @@
 // Decomposition: 64-row blocks.  One workgroup per block and per sweep; the
 // workgroup that owns block i of the forward sweep accumulates the products
 // L_ij y_j of every finished block j < i (four waves, 16 columns each) as soon
-// as block j publishes its result, then one wave finishes the block by
-// row-by-row substitution inside the diagonal block (each component rounded
-// to the solve's format, exactly as plain substitution does), stores it and
-// releases a flag.  Backward blocks run the same scheme from the last block
-// upwards and start as soon as their forward block is ready.  Workgroups take
-// a ticket from a device counter when they start, and ticket order decides
-// which block they own, so a workgroup only ever waits for workgroups that are
-// already running: the launch cannot deadlock whatever the dispatch order.
-// Every wait is bounded; on time-out the launch still drains and reports an
-// error.  Inner products are accumulated in float64 (double-double when the
-// solve's format is double-double).
+// as block j's values appear, then one wave finishes the block by row-by-row
+// substitution inside the diagonal block (each component rounded to the
+// solve's format, exactly as plain substitution does) and publishes it.
+// Backward blocks run the same scheme from the last block upwards and start as
+// soon as their forward block is ready.
+//
+// Publication: every solved component is written as self-validating 64-bit
+// words (one 32-bit half of the value next to the launch's 32-bit epoch) with
+// relaxed device-scope atomic stores, and readers poll the words themselves:
+// one memory round trip per block on the critical path, no separate flag and
+// no device-wide fences.  Workgroups take a ticket from a device counter when
+// they start, and ticket order decides which block they own, so a workgroup
+// only ever waits for workgroups that are already running: the launch cannot
+// deadlock whatever the dispatch order.  Every wait is bounded; on time-out the
+// launch still drains and sets an error word the host checks.  Inner products
+// are accumulated in float64 (double-double when the solve's format is
+// double-double).
 #include "common.hpp"
 #include "msir_internal.hpp"
 
@@ -26,9 +32,10 @@ namespace msir {
 
 constexpr int TB = 64;
 constexpr int TNT = 256;
+constexpr long kSpinLimit = 1L << 22;
 
 struct TrsvK {
-  int n, ldw, comp, in_round, out_round, nblk;
+  int n, ldw, out_round, nblk;
   const void* W;
   const int* perm;
   const double* rinv;
@@ -43,31 +50,10 @@ struct TrsvK {
   unsigned long long* tickets;
   unsigned long long base;
   unsigned epoch;
-  unsigned* fflag;
-  unsigned* bflag;
   unsigned* err;
-  double* yf_hi;
-  double* yf_lo;
-  double* xb_hi;
-  double* xb_lo;
+  unsigned long long* mbf;   // forward results, 2 (4 for double-double) words per row
+  unsigned long long* mbb;   // backward results
 };
-
-__device__ __forceinline__ void wait_flag(const unsigned* f, unsigned epoch, unsigned* err) {
-  long spins = 0;
-  while (__hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != epoch) {
-    __builtin_amdgcn_s_sleep(2);
-    if (++spins > (1L << 22)) {
-      __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      break;
-    }
-  }
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-__device__ __forceinline__ void set_flag(unsigned* f, unsigned epoch) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __hip_atomic_store(f, epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
 
 // Broadcast lane `lane`'s value to the wave through scalar registers (lane uniform).
 __device__ __forceinline__ double bcast(double v, int lane) {
@@ -77,12 +63,60 @@ __device__ __forceinline__ double bcast(double v, int lane) {
   return __builtin_bit_cast(double, ((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
 }
 
-template <int P, bool DD>
+__device__ __forceinline__ void mb_store(unsigned long long* p, double v, unsigned epoch) {
+  const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
+  const unsigned long long e = (unsigned long long)epoch << 32;
+  __hip_atomic_store(p, e | (u & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_store(p + 1, e | (u >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Publish row `row`'s value (and low part for double-double).
+template <bool DD>
+__device__ __forceinline__ void mb_put(unsigned long long* mb, int row, double h, double l, unsigned epoch) {
+  constexpr int NW = DD ? 4 : 2;
+  mb_store(mb + (size_t)row * NW, h, epoch);
+  if (DD) mb_store(mb + (size_t)row * NW + 2, l, epoch);
+}
+
+__device__ __forceinline__ bool mb_load(const unsigned long long* p, unsigned epoch, double& v) {
+  const unsigned long long a = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  const unsigned long long b = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  v = __builtin_bit_cast(double, ((b & 0xffffffffull) << 32) | (a & 0xffffffffull));
+  return (unsigned)(a >> 32) == epoch && (unsigned)(b >> 32) == epoch;
+}
+
+// Every lane of the wave with `need` reads row `row` of the mailbox; the wave
+// polls until all of them hold this launch's words (lanes without `need` get 0).
+template <bool DD>
+__device__ __forceinline__ void mb_get(const unsigned long long* mb, int row, bool need, unsigned epoch,
+                                       unsigned* err, double& h, double& l) {
+  constexpr int NW = DD ? 4 : 2;
+  h = 0.0;
+  l = 0.0;
+  long spins = 0;
+  for (;;) {
+    bool ok = true;
+    if (need) {
+      ok = mb_load(mb + (size_t)row * NW, epoch, h);
+      if (DD) ok = mb_load(mb + (size_t)row * NW + 2, epoch, l) && ok;
+    }
+    if (__all(ok)) break;
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+}
+
+template <int P, int C>
 __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
+  constexpr bool DD = (C == P_DD);
   typedef typename Store<P>::T ST;
   const ST* W = (const ST*)a.W;
   const int tid = threadIdx.x;
   const int lr = tid & 63, g = tid >> 6;
+  const int gu = __builtin_amdgcn_readfirstlane(g);
   __shared__ unsigned long long s_ticket;
   __shared__ double sD[TB][TB + 1];         // diagonal block (L or U part), float64
   __shared__ double sPh[4][TB], sPl[4][TB];  // group partial sums
@@ -105,7 +139,8 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
   const int grow = r0 + lr;
   const bool rv = lr < rows;
 
-  // diagonal block into LDS: fwd -> strict lower part of W; bwd -> upper part
+  // diagonal block into LDS: fwd -> strict lower part of W; bwd -> upper part (zeros
+  // elsewhere and outside the matrix, so the substitution below runs all 64 steps)
   for (int e = tid; e < TB * TB; e += TNT) {
     const int i = e & 63, k = e >> 6;
     double v = 0.0;
@@ -117,30 +152,28 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
 
   double ph = 0.0, pl = 0.0;
   // The factor entries of the next off-diagonal block are loaded before waiting for
-  // that block's flag (they do not depend on it); only the solution values wait.
+  // that block's values (they do not depend on them).
   if (fwd) {
     double lv[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lv[q] = (blk > 0 && rv) ? Store<P>::to_d(W[(size_t)(16 * g + q) * a.ldw + grow]) : 0.0;
+    for (int q = 0; q < 16; ++q) lv[q] = (blk > 0 && rv) ? Store<P>::to_d(W[(size_t)(16 * gu + q) * a.ldw + grow]) : 0.0;
     for (int j = 0; j < blk; ++j) {
-      if (tid == 0) wait_flag(&a.fflag[j], a.epoch, a.err);
-      __syncthreads();
+      double yh, yl;
+      mb_get<DD>(a.mbf, j * TB + lr, true, a.epoch, a.err, yh, yl);
       double ln[16];
-      const int cn = (j + 1) * TB + 16 * g;
+      const int cn = (j + 1) * TB + 16 * gu;
 #pragma unroll
       for (int q = 0; q < 16; ++q) ln[q] = (j + 1 < blk && rv) ? Store<P>::to_d(W[(size_t)(cn + q) * a.ldw + grow]) : 0.0;
-      if (rv) {
-        const int cb = j * TB + 16 * g;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int c = cb + q;
-          if (!DD) {
-            ph = __fma_rn(lv[q], a.yf_hi[c], ph);
-          } else {
-            double p1, p2;
-            dd_mul_d(a.yf_hi[c], a.yf_lo[c], lv[q], p1, p2);
-            dd_add(ph, pl, p1, p2, ph, pl);
-          }
+      for (int q = 0; q < 16; ++q) {
+        const double vh = bcast(yh, 16 * gu + q);
+        if (!DD) {
+          ph = __fma_rn(lv[q], vh, ph);
+        } else {
+          const double vl = bcast(yl, 16 * gu + q);
+          double p1, p2;
+          dd_mul_d(vh, vl, lv[q], p1, p2);
+          dd_add(ph, pl, p1, p2, ph, pl);
         }
       }
 #pragma unroll
@@ -150,157 +183,145 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
     double uv[16];
     {
       const int j = nblk - 1;
-      const int cb = j * TB + 16 * g;
+      const int cb = j * TB + 16 * gu;
 #pragma unroll
       for (int q = 0; q < 16; ++q)
         uv[q] = (j > blk && rv && cb + q < a.n) ? Store<P>::to_d(W[(size_t)(cb + q) * a.ldw + grow]) : 0.0;
     }
     for (int j = nblk - 1; j > blk; --j) {
-      if (tid == 0) wait_flag(&a.bflag[j], a.epoch, a.err);
-      __syncthreads();
+      double xh, xl;
+      mb_get<DD>(a.mbb, j * TB + lr, j * TB + lr < a.n, a.epoch, a.err, xh, xl);
       double un[16];
-      const int cn = (j - 1) * TB + 16 * g;
+      const int cn = (j - 1) * TB + 16 * gu;
 #pragma unroll
       for (int q = 0; q < 16; ++q)
         un[q] = (j - 1 > blk && rv) ? Store<P>::to_d(W[(size_t)(cn + q) * a.ldw + grow]) : 0.0;
-      if (rv) {
-        const int cb = j * TB + 16 * g;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int c = cb + q;
-          if (c < a.n) {
-            if (!DD) {
-              ph = __fma_rn(uv[q], a.xb_hi[c], ph);
-            } else {
-              double p1, p2;
-              dd_mul_d(a.xb_hi[c], a.xb_lo[c], uv[q], p1, p2);
-              dd_add(ph, pl, p1, p2, ph, pl);
-            }
-          }
+      for (int q = 0; q < 16; ++q) {
+        const double vh = bcast(xh, 16 * gu + q);
+        if (!DD) {
+          ph = __fma_rn(uv[q], vh, ph);
+        } else {
+          const double vl = bcast(xl, 16 * gu + q);
+          double p1, p2;
+          dd_mul_d(vh, vl, uv[q], p1, p2);
+          dd_add(ph, pl, p1, p2, ph, pl);
         }
       }
 #pragma unroll
       for (int q = 0; q < 16; ++q) uv[q] = un[q];
     }
-    if (tid == 0) wait_flag(&a.fflag[blk], a.epoch, a.err);
   }
   sPh[g][lr] = ph;
   sPl[g][lr] = pl;
   __syncthreads();
+  if (g != 0) return;
 
-  if (g == 0) {
-    // total of the off-diagonal products for row lr (fixed order)
-    double th = 0.0, tl = 0.0;
-    for (int q = 0; q < 4; ++q) {
-      if (!DD) th = __dadd_rn(th, sPh[q][lr]);
-      else dd_add(th, tl, sPh[q][lr], sPl[q][lr], th, tl);
-    }
-    // right-hand side of the block
-    double ah = 0.0, al = 0.0;
+  // total of the off-diagonal products for row lr (fixed order)
+  double th = 0.0, tl = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (!DD) th = __dadd_rn(th, sPh[q][lr]);
+    else dd_add(th, tl, sPh[q][lr], sPl[q][lr], th, tl);
+  }
+  // right-hand side of the block
+  double ah = 0.0, al = 0.0;
+  if (fwd) {
     if (rv) {
-      if (fwd) {
-        const int src = a.perm[grow];
-        double sc = a.R ? a.R[src] : 1.0;
-        ah = sc * a.t_hi[src];
-        if (DD) al = a.t_lo ? sc * a.t_lo[src] : 0.0;
-        else ah = round_to(ah, a.in_round);
-      } else {
-        ah = a.yf_hi[grow];
-        if (DD) al = a.yf_lo[grow];
-      }
-      if (!DD) ah = __dsub_rn(ah, th);
-      else dd_add(ah, al, -th, -tl, ah, al);
+      const int src = a.perm[grow];
+      const double sc = a.R ? a.R[src] : 1.0;
+      ah = sc * a.t_hi[src];
+      if (DD) al = a.t_lo ? sc * a.t_lo[src] : 0.0;
+      else ah = round_c<C>(ah);
     }
-    double yh = 0.0, yl = 0.0;
-    if (fwd) {
-      for (int c = 0; c < rows; ++c) {
-        double vh, vl = 0.0;
-        if (!DD) {
-          vh = bcast(round_to(ah, a.comp), c);
+  } else {
+    mb_get<DD>(a.mbf, grow, rv, a.epoch, a.err, ah, al);
+  }
+  if (rv) {
+    if (!DD) ah = __dsub_rn(ah, th);
+    else dd_add(ah, al, -th, -tl, ah, al);
+  }
+  double yh = 0.0, yl = 0.0;
+  if (fwd) {
+    // unit lower: y_c = fl(a_c), then a_i -= l_ic y_c for the rows below
+#pragma unroll 16
+    for (int c = 0; c < TB; ++c) {
+      const double l = sD[lr][c];
+      if (!DD) {
+        const double vh = bcast(round_c<C>(ah), c);
+        yh = (lr == c) ? vh : yh;
+        ah = __dsub_rn(ah, __dmul_rn(l, vh));
+      } else {
+        const double vh = bcast(ah, c), vl = bcast(al, c);
+        yh = (lr == c) ? vh : yh;
+        yl = (lr == c) ? vl : yl;
+        double p1, p2;
+        dd_mul_d(vh, vl, l, p1, p2);
+        dd_add(ah, al, -p1, -p2, ah, al);
+      }
+    }
+    if (rv) mb_put<DD>(a.mbf, grow, yh, yl, a.epoch);
+  } else {
+    const double ri = rv ? a.rinv[grow] : 0.0;
+    const double uii = rv ? Store<P>::to_d(W[(size_t)grow * a.ldw + grow]) : 1.0;
+#pragma unroll 16
+    for (int c = TB - 1; c >= 0; --c) {
+      const double u = sD[lr][c];
+      if (!DD) {
+        const double vh = bcast(round_c<C>(__dmul_rn(ah, ri)), c);
+        yh = (lr == c) ? vh : yh;
+        ah = __dsub_rn(ah, __dmul_rn(u, vh));
+      } else {
+        double qh, ql;
+        dd_div_d(ah, al, uii, qh, ql);
+        const double vh = bcast(qh, c), vl = bcast(ql, c);
+        yh = (lr == c) ? vh : yh;
+        yl = (lr == c) ? vl : yl;
+        double p1, p2;
+        dd_mul_d(vh, vl, u, p1, p2);
+        dd_add(ah, al, -p1, -p2, ah, al);
+      }
+    }
+    if (rv) {
+      mb_put<DD>(a.mbb, grow, yh, yl, a.epoch);
+      const double sc = a.S ? a.S[grow] : 1.0;
+      const double oh = a.mu * (sc * yh);
+      if (!DD) {
+        a.y_hi[grow] = a.out_round >= 0 ? round_to(oh, a.out_round) : oh;
+      } else {
+        const double ol = a.mu * (sc * yl);
+        if (a.out_round >= 0 && a.out_round != P_DD) {
+          a.y_hi[grow] = round_to(__dadd_rn(oh, ol), a.out_round);
         } else {
-          vh = bcast(ah, c);
-          vl = bcast(al, c);
-        }
-        if (lr == c) { yh = vh; yl = vl; }
-        if (lr > c) {
-          const double l = sD[lr][c];
-          if (!DD) ah = __dsub_rn(ah, __dmul_rn(l, vh));
-          else {
-            double p1, p2;
-            dd_mul_d(vh, vl, l, p1, p2);
-            dd_add(ah, al, -p1, -p2, ah, al);
-          }
+          a.y_hi[grow] = oh;
+          if (a.y_lo) a.y_lo[grow] = ol;
         }
       }
-      if (rv) {
-        a.yf_hi[grow] = yh;
-        if (DD) a.yf_lo[grow] = yl;
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (lr == 0) set_flag(&a.fflag[blk], a.epoch);
-    } else {
-      const double ri = rv ? a.rinv[grow] : 0.0;
-      const double uii = rv ? Store<P>::to_d(W[(size_t)grow * a.ldw + grow]) : 1.0;
-      for (int c = rows - 1; c >= 0; --c) {
-        double vh, vl = 0.0;
-        if (!DD) {
-          vh = bcast(round_to(__dmul_rn(ah, ri), a.comp), c);
-        } else {
-          double qh, ql;
-          dd_div_d(ah, al, uii, qh, ql);
-          vh = bcast(qh, c);
-          vl = bcast(ql, c);
-        }
-        if (lr == c) { yh = vh; yl = vl; }
-        if (lr < c) {
-          const double u = sD[lr][c];
-          if (!DD) ah = __dsub_rn(ah, __dmul_rn(u, vh));
-          else {
-            double p1, p2;
-            dd_mul_d(vh, vl, u, p1, p2);
-            dd_add(ah, al, -p1, -p2, ah, al);
-          }
-        }
-      }
-      if (rv) {
-        a.xb_hi[grow] = yh;
-        if (DD) a.xb_lo[grow] = yl;
-        const double sc = a.S ? a.S[grow] : 1.0;
-        double oh = a.mu * (sc * yh);
-        if (!DD) {
-          a.y_hi[grow] = a.out_round >= 0 ? round_to(oh, a.out_round) : oh;
-        } else {
-          double ol = a.mu * (sc * yl);
-          if (a.out_round >= 0 && a.out_round != P_DD) {
-            a.y_hi[grow] = round_to(__dadd_rn(oh, ol), a.out_round);
-          } else {
-            a.y_hi[grow] = oh;
-            if (a.y_lo) a.y_lo[grow] = ol;
-          }
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (lr == 0) set_flag(&a.bflag[blk], a.epoch);
     }
   }
 }
 
 template <int P>
-static void launch_trsv(Ctx& c, const TrsvK& k, int grid, bool dd) {
-  if (dd) MSIR_TIMED(c, 3, (k_trsv<P, true><<<grid, TNT, 0, c.stream>>>(k)));
-  else MSIR_TIMED(c, 3, (k_trsv<P, false><<<grid, TNT, 0, c.stream>>>(k)));
+static void launch_trsv(Ctx& c, const TrsvK& k, int grid, int comp) {
+  switch (comp) {
+    case P_FP16: MSIR_TIMED(c, MSIR_T_TRSV, (k_trsv<P, P_FP16><<<grid, TNT, 0, c.stream>>>(k))); break;
+    case P_BF16: MSIR_TIMED(c, MSIR_T_TRSV, (k_trsv<P, P_BF16><<<grid, TNT, 0, c.stream>>>(k))); break;
+    case P_FP32: MSIR_TIMED(c, MSIR_T_TRSV, (k_trsv<P, P_FP32><<<grid, TNT, 0, c.stream>>>(k))); break;
+    case P_FP64: MSIR_TIMED(c, MSIR_T_TRSV, (k_trsv<P, P_FP64><<<grid, TNT, 0, c.stream>>>(k))); break;
+    default: MSIR_TIMED(c, MSIR_T_TRSV, (k_trsv<P, P_DD><<<grid, TNT, 0, c.stream>>>(k))); break;
+  }
 }
 
 int trsv(Ctx& c, const TrsvArgs& a) {
   const int n = a.n;
+  if (a.comp < P_FP16 || a.comp > P_DD) return -3;
   const int nblk = (n + TB - 1) / TB;
-  unsigned* flags = (unsigned*)c.grow(c.flags, (2 * (size_t)nblk + 2) * sizeof(unsigned));
-  double* yf = (double*)c.grow(c.yfwd, 2 * (size_t)n * sizeof(double));
-  double* xb = (double*)c.grow(c.xbwd, 2 * (size_t)n * sizeof(double));
-  if (!flags || !yf || !xb) return MSIR_ERR_ALLOC;
+  unsigned* flags = (unsigned*)c.grow(c.flags, 16 * sizeof(unsigned));
+  unsigned long long* mbf = (unsigned long long*)c.grow(c.yfwd, 4 * (size_t)n * sizeof(unsigned long long));
+  unsigned long long* mbb = (unsigned long long*)c.grow(c.xbwd, 4 * (size_t)n * sizeof(unsigned long long));
+  if (!flags || !mbf || !mbb) return MSIR_ERR_ALLOC;
   TrsvK k;
-  k.n = n; k.ldw = a.ldw; k.comp = a.comp; k.out_round = a.out_round; k.nblk = nblk;
-  k.in_round = a.comp;
+  k.n = n; k.ldw = a.ldw; k.out_round = a.out_round; k.nblk = nblk;
   k.W = a.W; k.perm = a.perm; k.rinv = a.rinv; k.R = a.R; k.S = a.S; k.mu = a.mu;
   k.t_hi = a.t_hi; k.t_lo = a.t_lo; k.y_hi = a.y_hi; k.y_lo = a.y_lo; k.skip = a.skip;
   k.tickets = c.tickets;
@@ -310,20 +331,30 @@ int trsv(Ctx& c, const TrsvArgs& a) {
   c.epoch += 1;
   if (c.epoch == 0) c.epoch = 1;
   k.epoch = c.epoch;
-  k.fflag = flags;
-  k.bflag = flags + nblk;
-  k.err = flags + 2 * nblk;
-  k.yf_hi = yf; k.yf_lo = yf + n;
-  k.xb_hi = xb; k.xb_lo = xb + n;
-  const bool dd = a.comp == P_DD;
+  k.err = flags;
+  k.mbf = mbf;
+  k.mbb = mbb;
   switch (a.prec) {
-    case P_FP16: launch_trsv<P_FP16>(c, k, grid, dd); break;
-    case P_BF16: launch_trsv<P_BF16>(c, k, grid, dd); break;
-    case P_FP32: launch_trsv<P_FP32>(c, k, grid, dd); break;
-    case P_FP64: launch_trsv<P_FP64>(c, k, grid, dd); break;
+    case P_FP16: launch_trsv<P_FP16>(c, k, grid, a.comp); break;
+    case P_BF16: launch_trsv<P_BF16>(c, k, grid, a.comp); break;
+    case P_FP32: launch_trsv<P_FP32>(c, k, grid, a.comp); break;
+    case P_FP64: launch_trsv<P_FP64>(c, k, grid, a.comp); break;
     default: return -3;
   }
   HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
+// Error word of the substitution launches since the last check (0: none; 1: a wait
+// timed out; 2: ticket mismatch); cleared after reading.  Synchronises the stream.
+int trsv_check(Ctx& c, unsigned* out) {
+  *out = 0;
+  if (!c.flags.p) return 0;
+  unsigned h = 0;
+  HIP_CHECK(hipMemcpyAsync(&h, c.flags.p, sizeof(unsigned), hipMemcpyDeviceToHost, c.stream));
+  HIP_CHECK(hipStreamSynchronize(c.stream));
+  if (h) HIP_CHECK(hipMemsetAsync(c.flags.p, 0, sizeof(unsigned), c.stream));
+  *out = h;
   return 0;
 }
 

@@ -85,7 +85,7 @@ _SIG = {
     "msir_timing_get": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D)]),
 }
 
-TIMERS = ["panel", "swap", "gemm", "trsv", "matvec", "resid", "arnoldi", "other"]
+TIMERS = ["panel", "swap", "gemm", "trsv", "matvec", "resid", "arnoldi", "trgemv", "other"]
 
 
 def lib(path=None):
