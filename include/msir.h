@@ -218,6 +218,13 @@ MSIR_API int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int 
                const double* dR, const double* dS, double mu, msir_prec comp, int mode,
                const double* dt, double* dy);
 
+/* fl_p(x) elementwise: each of the n float64 values in dx rounded to format p
+ * (round to nearest, ties to even; magnitudes beyond the format's largest finite
+ * value become infinities; NaN stays NaN), written as float64 to dy (may equal
+ * dx).  p in FP16 / BF16 / FP32 / FP64 / DD (the last two leave values unchanged).
+ * This is the rounding every fl_u(.) / fl_{u_f}(.) of the method uses (Sec. 2).  */
+MSIR_API int msir_round(msir_handle* h, int n, msir_prec p, const double* dx, double* dy);
+
 /* Residual r = b - A x in ur (FP64 or DD), s = ||r||_inf, and the scaled residual
  * r_hat = fl_u(r / s) (Alg. 4 residual line and Sec. 2.1.2).  drhat: n float64
  * holding u values.  *s receives s (host).                                        */

@@ -255,7 +255,7 @@ int residual(Ctx& c, int n, const double* A, int lda, const double* x, const dou
 // ------------------------------------------------------------------ A v in precision p
 // y = A v with p in {FP32 (Au = fp32 copy of A), FP64, DD}; v holds values in u (float64 array).
 int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
-           double* y_hi, double* y_lo, const int* skip) {
+           double* y_hi, double* y_lo, const int* skip, const int* operm, const double* oR) {
   const GemvPlan g = gemv_plan(n, 0);
   double* ph = c.ws_part_hi(g.ns * (size_t)n);
   double* pl = c.ws_part_lo(g.ns * (size_t)n);
@@ -264,7 +264,7 @@ int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, c
   int rc;
   if (p == P_FP32) rc = gemv_partials(c, g, n, P_FP32, Au, ldau, v, nullptr, nullptr, 0, ph, pl, nullptr, skip);
   else rc = gemv_partials(c, g, n, P_FP64, A, lda, v, nullptr, nullptr, p == P_DD ? 1 : 0, ph, pl, nullptr, skip);
-  if (!rc) rc = gemv_finish(c, g, n, ph, pl, 1.0, nullptr, p, y_hi, y_lo, skip);
+  if (!rc) rc = gemv_finish(c, g, n, ph, pl, 1.0, nullptr, p, y_hi, y_lo, skip, operm, oR);
   c.tend(_slot);
   return rc;
 }

@@ -2,8 +2,10 @@
 //
 // Rounding: every conversion into a narrower format is a single IEEE
 // round-to-nearest-even of the exact source value (Table 3 formats; bf16 of
-// Sec. 2.2).  float64 -> fp16/bf16 goes through a round-to-odd float32
-// intermediate, which makes the second rounding exact (24 >= 11 + 2 bits).
+// Sec. 2.2).  Stored fp16/bf16 values come from float64 through a round-to-odd
+// float32 intermediate, which makes the second rounding exact (24 >= 11 + 2
+// bits); values that stay float64 (fl_u of the method) are rounded in float64
+// arithmetic (round_rne_small).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -65,11 +67,39 @@ __device__ __forceinline__ float f16_bits_to_f32(uint16_t h) {
 __device__ __forceinline__ uint16_t f64_to_f16_bits(double x) { return f32_to_f16_bits(f64_to_f32_rto(x)); }
 __device__ __forceinline__ uint16_t f64_to_bf16_bits(double x) { return f32_to_bf16_bits(f64_to_f32_rto(x)); }
 
+// Round-to-nearest-even of a float64 value to a binary format with PREC significand
+// bits, minimum normal exponent EMIN and largest finite value XMAX, done in float64:
+// with q the exponent of the target quantum (ulp of x's binade, or of the subnormal
+// range), adding and subtracting sigma = 1.5 * 2^(q+52) rounds x to a multiple of 2^q
+// (ties to even) exactly, because x + sigma stays in [2^(q+52), 2^(q+53)).  Results
+// beyond XMAX become infinities; the sign of x is kept (also for zero results).  The
+// binade is clamped to [EMIN, EMAX] so that sigma stays finite for every input
+// (larger magnitudes, infinities and NaN then fall through to the overflow test).
+template <int PREC, int EMIN, int EMAX>
+__device__ __forceinline__ double round_rne_small(double x, double xmax) {
+  int ex = __builtin_amdgcn_frexp_exp(x) - 1;   // 2^ex <= |x| < 2^(ex+1) for finite x
+  ex = ex < EMIN ? EMIN : (ex > EMAX ? EMAX : ex);
+  const int q = ex - (PREC - 1);
+  const double sigma = __builtin_amdgcn_ldexp(1.5, q + 52);
+  double y = __dsub_rn(__dadd_rn(x, sigma), sigma);
+  if (fabs(y) > xmax) y = __builtin_inf();
+  return __builtin_copysign(y, x);
+}
+
+// Round to format U (compile-time), returned as float64.
+template <int U>
+__device__ __forceinline__ double round_c(double x) {
+  if constexpr (U == P_FP16) return round_rne_small<11, -14, 15>(x, 65504.0);
+  else if constexpr (U == P_BF16) return round_rne_small<8, -126, 127>(x, 3.3895313892515355e38);
+  else if constexpr (U == P_FP32) return (double)(float)x;
+  else return x;
+}
+
 // Round a float64 value to format p, returned as float64 (DD/FP64: unchanged).
 __device__ __forceinline__ double round_to(double x, int p) {
   switch (p) {
-    case P_FP16: return (double)f16_bits_to_f32(f64_to_f16_bits(x));
-    case P_BF16: return (double)bf16_bits_to_f32(f64_to_bf16_bits(x));
+    case P_FP16: return round_c<P_FP16>(x);
+    case P_BF16: return round_c<P_BF16>(x);
     case P_FP32: return (double)(float)x;
     default: return x;
   }
@@ -199,13 +229,20 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Round to format U (compile-time), returned as float64.
-template <int U>
-__device__ __forceinline__ double round_c(double x) {
-  if constexpr (U == P_FP16) return (double)f16_bits_to_f32(f64_to_f16_bits(x));
-  else if constexpr (U == P_BF16) return (double)bf16_bits_to_f32(f64_to_bf16_bits(x));
-  else if constexpr (U == P_FP32) return (double)(float)x;
-  else return x;
+// Sum of the 16 per-wave partials p[0..15] (LDS), uniform over the calling wave:
+// lane k < 16 reads p[k] and four DPP steps fold them (fixed order).  Only 128 bytes
+// of LDS are read per wave, instead of every lane reading all sixteen values.
+__device__ __forceinline__ double sum16_lanes(const double* p) {
+  const int lane = threadIdx.x & 63;
+  double v = lane < 16 ? p[lane] : 0.0;
+  v = __dadd_rn(v, dpp_d<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
+  v = __dadd_rn(v, dpp_d<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
+  v = __dadd_rn(v, dpp_d<0x141, 0xF>(v));   // row_half_mirror
+  v = __dadd_rn(v, dpp_d<0x140, 0xF>(v));   // row_mirror: lanes 0..15 hold the total
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 0);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 0);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
 // Ordered folds of strided partial sums p[s * stride] for s in [s_lo, s_hi): the

@@ -29,14 +29,15 @@
 
 namespace msir {
 
-constexpr int GV_WAVES = 16;                 // waves (column groups) per workgroup
-constexpr int GV_T = 64 * GV_WAVES;          // threads per workgroup
 constexpr int GV_ROWS = 256;                 // rows per workgroup (4 per lane)
 constexpr int GV_MAXCHUNK = 2048;            // columns per slice (LDS staging bound)
 constexpr int GV_TARGET = 256;               // busy workgroups per launch
+constexpr int GV_BATCH = 128;                // slice widths are multiples of this
 
+// Four consecutive rows of one column in the matrix's own type (one 16-byte load for
+// fp32, two for fp64, when aligned and all four rows exist).
 template <typename TA>
-__device__ __forceinline__ void load4(const TA* __restrict__ p, bool vec, int valid, double v[4]) {
+__device__ __forceinline__ void load4(const TA* __restrict__ p, bool vec, int valid, TA v[4]) {
   if constexpr (sizeof(TA) == 4) {
     if (vec) {
       const float4 q = *reinterpret_cast<const float4*>(p);
@@ -52,7 +53,7 @@ __device__ __forceinline__ void load4(const TA* __restrict__ p, bool vec, int va
     }
   }
 #pragma unroll
-  for (int e = 0; e < 4; ++e) v[e] = (e < valid) ? (double)p[e] : 0.0;
+  for (int e = 0; e < 4; ++e) v[e] = (e < valid) ? p[e] : TA(0);
 }
 
 // Does lane row block [r0, r0+4) need column j of a TRI-triangular operand?
@@ -90,8 +91,11 @@ __device__ __forceinline__ void slice_range(int n, int rb, int s, int chunk, int
 
 // part_hi[s * n + row] (and part_lo, part_x by MODE) = sum over slice s of T[row, j] xin[j],
 // xin[j] = perm ? R[perm[j]] x[perm[j]] (R may be null) : x[j].
-template <typename TA, int MODE, int TRI>
-__global__ __launch_bounds__(GV_T) void k_gemv(int n, const TA* __restrict__ A, int lda, bool aligned,
+// WV waves per workgroup (column groups): 16 for fp32 matrices and the double-double
+// modes, 8 for plain float64 products (whose eight 32-byte columns in flight per
+// lane need the larger register budget of a 512-thread workgroup).
+template <typename TA, int MODE, int TRI, int WV>
+__global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ A, int lda, bool aligned,
                                                const double* __restrict__ x, const int* __restrict__ perm,
                                                const double* __restrict__ R, int chunk,
                                                double* __restrict__ p_hi, double* __restrict__ p_lo,
@@ -104,40 +108,57 @@ __global__ __launch_bounds__(GV_T) void k_gemv(int n, const TA* __restrict__ A, 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr int GV_WAVES = WV, GV_T = 64 * WV;
   constexpr int NB = (MODE == 0) ? 1 : 2;
+  constexpr int XPT = GV_MAXCHUNK / GV_T;
   __shared__ double lds[NB * GV_WAVES * GV_ROWS];   // x slice first, then the wave sums
   double* sx = lds;
-  for (int t = tid; t < j1 - j0; t += GV_T) {
-    const int j = j0 + t;
-    double v;
-    if (perm) { const int q = perm[j]; v = R ? R[q] * x[q] : x[q]; } else v = x[j];
-    sx[t] = v;
+  const int len = j1 - j0;
+  // 1. loads of this workgroup's x slice (clamped indices, issued unconditionally)
+  double xs[XPT];
+#pragma unroll
+  for (int q = 0; q < XPT; ++q) {
+    const int jj = j0 + min(tid + q * GV_T, len - 1);
+    if (perm) { const int pq = perm[jj]; xs[q] = R ? R[pq] * x[pq] : x[pq]; } else xs[q] = x[jj];
   }
-  __syncthreads();
+  // 2. the first batch of matrix columns, in flight before the slice is needed
   const int rlo = rb * GV_ROWS;
   const int r0 = rlo + 4 * lane;
   const int valid = max(0, min(4, n - r0));
   const bool vec = aligned && valid == 4;
-  double h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0}, f[4] = {0, 0, 0, 0};
-  constexpr int UNR = (MODE == 0) ? 8 : 4;
+  const TA* a = A + min(r0, n - 1);
+  constexpr int UNR = (sizeof(TA) == 4 || MODE == 0) ? 8 : 4;   // columns in flight per lane
+  static_assert(UNR * GV_WAVES <= GV_BATCH && GV_BATCH % (UNR * GV_WAVES) == 0, "slices must be whole batches");
+  TA v[UNR][4];
+  int j = j0 + w;
   if (valid > 0) {
-    const TA* a = A + r0;
-    int j = j0 + w;
-    for (; j + (UNR - 1) * GV_WAVES < j1; j += UNR * GV_WAVES) {
-      double v[UNR][4];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) load4<TA>(a + (size_t)min(j + u * GV_WAVES, j1 - 1) * lda, vec, valid, v[u]);
+  }
+  // 3. slice into LDS
+#pragma unroll
+  for (int q = 0; q < XPT; ++q)
+    if (tid + q * GV_T < len) sx[tid + q * GV_T] = xs[q];
+  __syncthreads();
+  // 4. batches of UNR columns per wave: accumulate the batch (columns past the slice or
+  // outside the triangle contribute exact zeros), then load the next one
+  double h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0}, f[4] = {0, 0, 0, 0};
+  if (valid > 0) {
+    for (;;) {
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
-        const int jj = j + u * GV_WAVES;
-        if (needs<TRI>(jj, r0)) load4<TA>(a + (size_t)jj * lda, vec, valid, v[u]);
-        else v[u][0] = v[u][1] = v[u][2] = v[u][3] = 0.0;
-      }
+        const int col = j + u * GV_WAVES;
+        const bool ok = col < j1 && needs<TRI>(col, r0);
+        const double xv = ok ? sx[min(col, j1 - 1) - j0] : 0.0;
+        double vv[4];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) accum<MODE>(v[u], sx[j + u * GV_WAVES - j0], h, l, f);
-    }
-    for (; j < j1; j += GV_WAVES) {
-      double v[4] = {0, 0, 0, 0};
-      if (needs<TRI>(j, r0)) load4<TA>(a + (size_t)j * lda, vec, valid, v);
-      accum<MODE>(v, sx[j - j0], h, l, f);
+        for (int e = 0; e < 4; ++e) vv[e] = ok ? (double)v[u][e] : 0.0;
+        accum<MODE>(vv, xv, h, l, f);
+      }
+      j += UNR * GV_WAVES;
+      if (j >= j1) break;
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) load4<TA>(a + (size_t)min(j + u * GV_WAVES, j1 - 1) * lda, vec, valid, v[u]);
     }
   }
   // fold the 16 waves' sums in wave order (LDS reused: wait until every wave is done with sx)
@@ -175,14 +196,18 @@ __global__ __launch_bounds__(GV_T) void k_gemv(int n, const TA* __restrict__ A, 
 // y_i = round_p(oscale_i * sum_s part[s][i]) over the slices that met row i's block,
 // oscale_i = S ? mu * S[i] : 1 (float64 products); for p == DD the double-double
 // sum goes to y_hi / y_lo.
+// With operm (p != DD), slot i receives row q = operm[i] scaled by oR[q] (float64
+// product, after the rounding): the permuted, row-scaled vector the next product reads.
 template <int TRI>
 __global__ __launch_bounds__(256) void k_gemv_finish(int n, int ns, int chunk, const double* __restrict__ p_hi,
                                                      const double* __restrict__ p_lo, double mu,
-                                                     const double* __restrict__ S, int p, double* __restrict__ y_hi,
+                                                     const double* __restrict__ S, int p, const int* __restrict__ operm,
+                                                     const double* __restrict__ oR, double* __restrict__ y_hi,
                                                      double* __restrict__ y_lo, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  if (i >= n) return;
+  const int slot = blockIdx.x * 256 + threadIdx.x;
+  if (slot >= n) return;
+  const int i = operm ? operm[slot] : slot;
   const int rb = i / GV_ROWS;
   int s_lo = 0, s_hi = ns;
   if (TRI == 1) s_hi = (min(n, (rb + 1) * GV_ROWS) + chunk - 1) / chunk;
@@ -190,12 +215,14 @@ __global__ __launch_bounds__(256) void k_gemv_finish(int n, int ns, int chunk, c
   if (p != P_DD) {
     double t = fold_sum(p_hi + i, (size_t)n, s_lo, s_hi);
     if (S) t = mu * (S[i] * t);
-    y_hi[i] = round_to(t, p);
+    t = round_to(t, p);
+    if (oR) t = oR[i] * t;
+    y_hi[slot] = t;
   } else {
     double th = 0.0, tl = 0.0;
     fold_dd(p_hi + i, p_lo + i, (size_t)n, s_lo, s_hi, 1.0, th, tl);
-    y_hi[i] = th;
-    y_lo[i] = tl;
+    y_hi[slot] = th;
+    y_lo[slot] = tl;
   }
 }
 
@@ -210,8 +237,11 @@ GemvPlan gemv_plan(int n, int tri) {
     const int rlo = r * GV_ROWS, rhi = n < rlo + GV_ROWS ? n : rlo + GV_ROWS;
     cols += tri == 0 ? n : (tri == 1 ? rhi : n - rlo);
   }
+  // slices are whole batches (GV_BATCH columns: eight per wave), so no batch is
+  // partly empty except at the matrix edge
   long long chunk = (cols + GV_TARGET - 1) / GV_TARGET;
-  if (chunk < 4 * GV_WAVES) chunk = 4 * GV_WAVES;
+  chunk = (chunk + GV_BATCH / 2) / GV_BATCH * GV_BATCH;
+  if (chunk < GV_BATCH) chunk = GV_BATCH;
   if (chunk > GV_MAXCHUNK) chunk = GV_MAXCHUNK;
   if (n > 0 && chunk > n) chunk = n;
   if (chunk < 1) chunk = 1;
@@ -223,14 +253,15 @@ GemvPlan gemv_plan(int n, int tri) {
 template <typename TA, int MODE>
 static void launch_gemv(Ctx& c, const GemvPlan& g, int n, const TA* A, int lda, const double* x, const int* perm,
                         const double* R, double* ph, double* pl, double* px, const int* skip) {
+  constexpr int WV = (sizeof(TA) == 8 && MODE == 0) ? 8 : 16;
   const bool aligned = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
   dim3 grid(g.rb, g.ns);
   if (g.tri == 0)
-    k_gemv<TA, MODE, 0><<<grid, GV_T, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
+    k_gemv<TA, MODE, 0, WV><<<grid, 64 * WV, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
   else if (g.tri == 1)
-    k_gemv<TA, MODE, 1><<<grid, GV_T, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
+    k_gemv<TA, MODE, 1, WV><<<grid, 64 * WV, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
   else
-    k_gemv<TA, MODE, 2><<<grid, GV_T, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
+    k_gemv<TA, MODE, 2, WV><<<grid, 64 * WV, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
 }
 
 int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const double* x,
@@ -252,15 +283,16 @@ int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, i
 }
 
 int gemv_finish(Ctx& c, const GemvPlan& g, int n, const double* ph, const double* pl, double mu, const double* S,
-                int p, double* y_hi, double* y_lo, const int* skip) {
+                int p, double* y_hi, double* y_lo, const int* skip, const int* operm, const double* oR) {
   if (n <= 0) return 0;
+  if (p == P_DD && operm) return -3;
   const int blocks = (n + 255) / 256;
   if (g.tri == 0)
-    k_gemv_finish<0><<<blocks, 256, 0, c.stream>>>(n, g.ns, g.chunk, ph, pl, mu, S, p, y_hi, y_lo, skip);
+    k_gemv_finish<0><<<blocks, 256, 0, c.stream>>>(n, g.ns, g.chunk, ph, pl, mu, S, p, operm, oR, y_hi, y_lo, skip);
   else if (g.tri == 1)
-    k_gemv_finish<1><<<blocks, 256, 0, c.stream>>>(n, g.ns, g.chunk, ph, pl, mu, S, p, y_hi, y_lo, skip);
+    k_gemv_finish<1><<<blocks, 256, 0, c.stream>>>(n, g.ns, g.chunk, ph, pl, mu, S, p, operm, oR, y_hi, y_lo, skip);
   else
-    k_gemv_finish<2><<<blocks, 256, 0, c.stream>>>(n, g.ns, g.chunk, ph, pl, mu, S, p, y_hi, y_lo, skip);
+    k_gemv_finish<2><<<blocks, 256, 0, c.stream>>>(n, g.ns, g.chunk, ph, pl, mu, S, p, operm, oR, y_hi, y_lo, skip);
   HIP_CHECK(hipGetLastError());
   return 0;
 }

@@ -6,10 +6,13 @@
 //  1. k_panel (one workgroup of 1024 threads): the m x nb panel is held in
 //     registers in the arithmetic format (fp32 for u_f in {fp16, bf16, fp32},
 //     fp64 for u_f = fp64), ceil(m/1024) rows per thread.  For each column the
-//     pivot search is a per-thread scan, a 64-lane shuffle butterfly on
-//     (|value|, position) and one LDS exchange between the 16 waves; the wave
-//     that owns the winning row publishes that row in LDS in the same step, so
-//     a column costs a single barrier.  Rows are not moved: each thread keeps
+//     pivot search is a per-thread scan, a DPP lane-move reduction of an
+//     ordering key (|value|, then lower position) within each wave and one LDS
+//     exchange between the 16 waves (read lane-parallel and folded by DPP); the
+//     wave that owns the winning row publishes that row in LDS in the same step,
+//     so a column costs a single barrier.  Values every lane needs (the pivot
+//     row) are read one per lane and broadcast by readlane: LDS return bandwidth,
+//     not latency, is what a 1024-thread broadcast read costs.  Rows are not moved: each thread keeps
 //     the current position of its rows and the interchange is a relabelling.
 //     Ties go to the lowest position, NaN never wins, a zero pivot column is
 //     recorded in info and left unscaled.  Multipliers use the correctly
@@ -46,57 +49,151 @@ template <int P> __device__ __forceinline__ typename Store<P>::T from_a(float v)
 template <int P> __device__ __forceinline__ typename Store<P>::T from_a(double v) { return Store<P>::from_d(v); }
 
 // ------------------------------------------------------------------ panel
+// Pivot candidates are compared by an ordering key: larger |value| first, then the
+// lower position; non-candidates and NaN get the key 0, below every candidate
+// (a candidate of value 0 still has a nonzero key).  |value| >= 0, so its IEEE bits
+// order like the values.  fp32: one 64-bit key (value bits, inverted position);
+// fp64: value bits plus the inverted position as a second word.
+template <typename AT> struct PivKey;
+template <> struct PivKey<float> {
+  uint64_t k;
+  __device__ static PivKey make(float av, int pos, bool cand) {
+    PivKey r;
+    r.k = (cand && av == av) ? (((uint64_t)__float_as_uint(av) << 32) | (uint32_t)(~pos)) : 0ull;
+    return r;
+  }
+  __device__ bool gt(const PivKey& o) const { return k > o.k; }
+  __device__ bool eq(const PivKey& o) const { return k == o.k; }
+  __device__ bool none() const { return k == 0ull; }
+  __device__ int pos() const { return (int)~(uint32_t)k; }
+  __device__ float val() const { return __uint_as_float((uint32_t)(k >> 32)); }
+  template <int CTRL, int RM> __device__ PivKey dpp() const {
+    PivKey r;
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)k, CTRL, RM, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k >> 32), CTRL, RM, 0xF, false);
+    r.k = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    return r;
+  }
+  __device__ PivKey lane(int l) const {
+    PivKey r;
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)k, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(k >> 32), l);
+    r.k = ((uint64_t)hi << 32) | lo;
+    return r;
+  }
+};
+template <> struct PivKey<double> {
+  uint64_t v;
+  uint32_t p;
+  __device__ static PivKey make(double av, int pos, bool cand) {
+    PivKey r;
+    const bool ok = cand && av == av;
+    r.v = ok ? __builtin_bit_cast(uint64_t, av) : 0ull;
+    r.p = ok ? (uint32_t)(~pos) : 0u;
+    return r;
+  }
+  __device__ bool gt(const PivKey& o) const { return v > o.v || (v == o.v && p > o.p); }
+  __device__ bool eq(const PivKey& o) const { return v == o.v && p == o.p; }
+  __device__ bool none() const { return p == 0u; }
+  __device__ int pos() const { return (int)~p; }
+  __device__ double val() const { return __builtin_bit_cast(double, v); }
+  template <int CTRL, int RM> __device__ PivKey dpp() const {
+    PivKey r;
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, RM, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, RM, 0xF, false);
+    r.v = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+    r.p = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)p, CTRL, RM, 0xF, false);
+    return r;
+  }
+  __device__ PivKey lane(int l) const {
+    PivKey r;
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    r.v = ((uint64_t)hi << 32) | lo;
+    r.p = __builtin_amdgcn_readlane((int)p, l);
+    return r;
+  }
+};
+
+__device__ __forceinline__ float bcast_a(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double bcast_a(double v, int l) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+template <typename K, int CTRL, int RM>
+__device__ __forceinline__ K kmax_step(K x) {
+  const K y = x.template dpp<CTRL, RM>();
+  return y.gt(x) ? y : x;
+}
+
+// Largest key of the wave (the DPP pattern of wave_sum_dpp with max), uniform.
+template <typename K>
+__device__ __forceinline__ K wave_max_key(K x) {
+  x = kmax_step<K, 0xB1, 0xF>(x);
+  x = kmax_step<K, 0x4E, 0xF>(x);
+  x = kmax_step<K, 0x141, 0xF>(x);
+  x = kmax_step<K, 0x140, 0xF>(x);
+  x = kmax_step<K, 0x142, 0xA>(x);
+  x = kmax_step<K, 0x143, 0xC>(x);
+  return x.lane(63);
+}
+
 template <int P, int R, int NB>
 __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
                                                int* __restrict__ ipiv, int* __restrict__ info,
                                                int* __restrict__ moved) {
   typedef typename Arith<P>::T AT;
-  typedef typename Store<P>::T ST;
+  typedef PivKey<AT> K;
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int m = n - j0;
   __shared__ AT srow[2][PNW][NB];
-  __shared__ AT sval[2][PNW];
-  __shared__ int spos[2][PNW];
+  __shared__ K skey[2][PNW];
 
   AT a[R][NB];
   int pos[R];
   bool valid[R];
+  {
+    // every load is issued unconditionally (row and column indices clamped into the
+    // panel) before any value is used, so the R x NB loads are all in flight at once
+    typename Store<P>::T raw[R][NB];
 #pragma unroll
-  for (int s = 0; s < R; ++s) {
-    const int r = tid + s * PNT;
-    valid[s] = r < m;
-    pos[s] = r;
+    for (int s = 0; s < R; ++s) {
+      const int r = tid + s * PNT;
+      const int rr = j0 + min(r, m - 1);
 #pragma unroll
-    for (int k = 0; k < NB; ++k)
-      a[s][k] = (valid[s] && k < jb) ? to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + r], AT(0)) : AT(0);
+      for (int k = 0; k < NB; ++k) raw[s][k] = W[(size_t)(j0 + min(k, jb - 1)) * ldw + rr];
+    }
+#pragma unroll
+    for (int s = 0; s < R; ++s) {
+      const int r = tid + s * PNT;
+      valid[s] = r < m;
+      pos[s] = r;
+#pragma unroll
+      for (int k = 0; k < NB; ++k) a[s][k] = (valid[s] && k < jb) ? to_a<P>(raw[s][k], AT(0)) : AT(0);
+    }
   }
 
 #pragma unroll
   for (int c = 0; c < NB; ++c) {
     if (c < jb) {
       const int buf = c & 1;
-      // local candidate: largest |a[s][c]| among active rows, lowest position on ties
-      AT bv = AT(-1);
-      int bp = 0x7fffffff;
-      int bs = -1;
+      // this thread's best candidate row, then the wave's
+      K best = K::make(AT(0), 0, false);
+      int bs = 0;
 #pragma unroll
       for (int s = 0; s < R; ++s) {
-        if (valid[s] && pos[s] >= c) {
-          AT v = fabs(a[s][c]);
-          if (v > bv || (v == bv && pos[s] < bp)) { bv = v; bp = pos[s]; bs = s; }
-        }
+        const K ks = K::make(fabs(a[s][c]), pos[s], valid[s] && pos[s] >= c);
+        if (ks.gt(best)) { best = ks; bs = s; }
       }
-      AT wvv = bv;
-      int wp = bp;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        AT ov = __shfl_xor(wvv, o, 64);
-        int op = __shfl_xor(wp, o, 64);
-        if (ov > wvv || (ov == wvv && op < wp)) { wvv = ov; wp = op; }
-      }
-      // the owner of the wave's best row publishes it
-      if (bs >= 0 && bp == wp && wvv >= AT(0)) {
+      const K wbest = wave_max_key(best);
+      // the owner of the wave's best row publishes it (one lane at most: positions differ)
+      if (!wbest.none() && best.eq(wbest)) {
 #pragma unroll
         for (int s = 0; s < R; ++s)
           if (s == bs) {
@@ -104,17 +201,20 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
             for (int k = c; k < NB; ++k) srow[buf][wv][k] = a[s][k];
           }
       }
-      if (lane == 0) { sval[buf][wv] = wvv; spos[buf][wv] = wp; }
+      if (lane == 0) skey[buf][wv] = wbest;
       __syncthreads();
-      AT gv = sval[buf][0];
-      int gp = spos[buf][0], gw = 0;
-#pragma unroll
-      for (int w = 1; w < PNW; ++w) {
-        AT v = sval[buf][w];
-        int p = spos[buf][w];
-        if (v > gv || (v == gv && p < gp)) { gv = v; gp = p; gw = w; }
-      }
-      if (gv < AT(0)) gp = c;  // no valid candidate (all NaN): no interchange
+      // lanes 0..15 read one wave's key each (128 bytes of LDS per wave, not 16 keys
+      // per lane); the largest is folded by DPP and the winning wave found by a ballot
+      const K kl = lane < PNW ? skey[buf][lane] : K::make(AT(0), 0, false);
+      K kr = kmax_step<K, 0xB1, 0xF>(kl);
+      kr = kmax_step<K, 0x4E, 0xF>(kr);
+      kr = kmax_step<K, 0x141, 0xF>(kr);
+      kr = kmax_step<K, 0x140, 0xF>(kr);
+      const K gbest = kr.lane(0);
+      const int gw = __ffsll((unsigned long long)__ballot(lane < PNW && kl.eq(gbest))) - 1;
+      const bool have = !gbest.none();
+      const int gp = have ? gbest.pos() : c;   // no candidate (all NaN): no interchange
+      const AT gv = have ? gbest.val() : AT(-1);
       if (tid == 0) {
         ipiv[j0 + c] = j0 + gp;
         if (!(gv > AT(0))) {
@@ -123,28 +223,27 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
       }
       // interchange = relabelling of positions c and gp
 #pragma unroll
-      for (int s = 0; s < R; ++s) {
-        if (pos[s] == c) pos[s] = gp;
-        else if (pos[s] == gp) pos[s] = c;
-      }
+      for (int s = 0; s < R; ++s) pos[s] = (pos[s] == c) ? gp : ((pos[s] == gp) ? c : pos[s]);
       if (gv > AT(0)) {
-        const AT piv = srow[buf][gw][c];
-        const AT rcp = a_rcp(piv);
+        // pivot row: lane k reads entry k, every entry is then broadcast by readlane
+        const AT prow = lane < NB ? srow[buf][gw][lane] : AT(0);
+        const AT rcp = a_rcp(bcast_a(prow, c));
         AT l[R];
         bool act[R];
 #pragma unroll
         for (int s = 0; s < R; ++s) {
           act[s] = valid[s] && pos[s] > c;
           l[s] = a_mul(a[s][c], rcp);
-          if (act[s]) a[s][c] = l[s];
+          a[s][c] = act[s] ? l[s] : a[s][c];
         }
+        // columns k >= jb hold zeros (loaded as such), so updating them is harmless
 #pragma unroll
         for (int k = c + 1; k < NB; ++k) {
-          if (k < jb) {
-            const AT pk = srow[buf][gw][k];
+          const AT pk = bcast_a(prow, k);
 #pragma unroll
-            for (int s = 0; s < R; ++s)
-              if (act[s]) a[s][k] = a_fma(-l[s], pk, a[s][k]);
+          for (int s = 0; s < R; ++s) {
+            const AT t = a_fma(-l[s], pk, a[s][k]);
+            a[s][k] = act[s] ? t : a[s][k];
           }
         }
       }

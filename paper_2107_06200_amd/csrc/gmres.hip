@@ -41,12 +41,13 @@ __global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __rest
 }
 
 // One modified Gram-Schmidt step against basis vector i held in B: h = <B, w> (one
-// barrier), w <- fl_u(w - h B); then B is refilled with v_{i+4} (if i + 4 <= j), so
-// four basis vectors are in flight while the inner products are reduced.
+// barrier), w <- fl_u(w - h B).  h goes to the LDS copy of the Hessenberg column
+// (sHc, when the column fits) or straight to H (stored by every lane, same value,
+// so that all waves issue the same memory operations).
 template <int G, int U>
-__device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], double (&B)[G],
-                                         const double* __restrict__ V, int ldv, double* __restrict__ H, int ldh,
-                                         double (*sh)[GNT / 64]) {
+__device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], const double (&B)[G],
+                                         double* __restrict__ H, int ldh, double (*sh)[GNT / 64], bool lds_col,
+                                         double* sHc) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   double acc = 0.0;
@@ -55,62 +56,85 @@ __device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], do
   acc = wave_sum_dpp(acc);
   if (lane == 0) sh[i & 1][wv] = acc;
   __syncthreads();
-  double h = 0.0;
-#pragma unroll
-  for (int q = 0; q < GNT / 64; ++q) h = __dadd_rn(h, sh[i & 1][q]);
+  const double h = sum16_lanes(sh[i & 1]);
 #pragma unroll
   for (int t = 0; t < G; ++t) {
-    const int r = tid + t * GNT;
-    if (r < n) w[t] = round_c<U>(__dsub_rn(w[t], __dmul_rn(h, B[t])));
+    const double nw = round_c<U>(__dsub_rn(w[t], __dmul_rn(h, B[t])));
+    w[t] = (tid + t * GNT < n) ? nw : 0.0;
   }
-  if (tid == 0) H[(size_t)j * ldh + i] = h;
-  if (i + 4 <= j) {
-    const double* vp = V + (size_t)(i + 4) * ldv;
+  if (lds_col) {
+    if (tid == 0) sHc[i] = h;
+  } else {
+    H[(size_t)j * ldh + i] = h;
+  }
+}
+
+// Load column c of V into B (row indices clamped to the matrix).
+template <int G>
+__device__ __forceinline__ void load_col(double (&B)[G], const double* __restrict__ V, int ldv, int c,
+                                         const int (&rc)[G]) {
+  const double* vp = V + (size_t)c * ldv;
 #pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const int r = tid + t * GNT;
-      B[t] = r < n ? vp[r] : 0.0;
-    }
-  }
+  for (int t = 0; t < G; ++t) B[t] = vp[rc[t]];
 }
 
 // Arnoldi step j: w (= M^{-1} A v_j, in u) is orthogonalised against v_0..v_j by
 // modified Gram-Schmidt, h_{j+1,j} = ||w||_2, the new Hessenberg column is rotated
 // by the previous Givens rotations and a new rotation zeroes h_{j+1,j}; g is
 // rotated and the stopping test |g_{j+1}| <= tau beta0 is taken.  G values per
-// thread (n <= G * GNT), U the working precision.
-template <int G, int U>
+// thread (n <= G * GNT), U the working precision.  The first JU inner products are
+// straight-line code with a ring of D basis vectors in flight (the refill of a slot
+// is issued right after the slot is consumed), so the loads of v_{i+D} overlap D
+// inner products; beyond JU a rolled loop loads each vector when it is needed.
+constexpr int JU = 64;
+constexpr int JL = 512;   // Hessenberg columns up to this length are rotated in LDS
+template <int G, int U, int D>
 __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restrict__ V, int ldv,
                                                  const double* __restrict__ w_in, double* __restrict__ H, int ldh,
                                                  double* __restrict__ cs, double* __restrict__ sn,
                                                  double* __restrict__ g, const double* __restrict__ beta0, double tau,
                                                  GStatus* st) {
+  static_assert(GNT / 64 == 16, "sum16_lanes folds sixteen wave partials");
   if (st->done) return;
   // per-wave partial sums, double-buffered by the parity of the inner-product index
   // so that one barrier per inner product suffices
   __shared__ double sh[2][GNT / 64];
+  // the Hessenberg column and the previous rotations, staged in LDS so that the
+  // serial rotation sweep below runs on LDS, not on global-memory round trips
+  __shared__ double sHc[JL], sCs[JL], sSn[JL];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  double w[G], b0[G], b1[G], b2[G], b3[G];
+  const bool lds_col = j + 2 <= JL;
+  {
+    const int t0 = min(tid, max(j - 1, 0));   // entries 0..j-1 exist
+    const double cv = cs[t0], sv = sn[t0];
+    if (lds_col && tid < j) { sCs[tid] = cv; sSn[tid] = sv; }
+  }
+  const double gj = g[j], b0 = *beta0;
+  int rc[G];
+  double w[G];
 #pragma unroll
   for (int t = 0; t < G; ++t) {
     const int r = tid + t * GNT;
-    const bool in = r < n;
-    w[t] = in ? w_in[r] : 0.0;
-    b0[t] = in ? V[r] : 0.0;
-    b1[t] = (in && j >= 1) ? V[(size_t)ldv + r] : 0.0;
-    b2[t] = (in && j >= 2) ? V[2 * (size_t)ldv + r] : 0.0;
-    b3[t] = (in && j >= 3) ? V[3 * (size_t)ldv + r] : 0.0;
+    rc[t] = min(r, n - 1);
+    const double v = w_in[rc[t]];
+    w[t] = r < n ? v : 0.0;
   }
-  for (int i = 0; i <= j; i += 4) {
-    mgs_step<G, U>(n, i, j, w, b0, V, ldv, H, ldh, sh);
-    if (i + 1 > j) break;
-    mgs_step<G, U>(n, i + 1, j, w, b1, V, ldv, H, ldh, sh);
-    if (i + 2 > j) break;
-    mgs_step<G, U>(n, i + 2, j, w, b2, V, ldv, H, ldh, sh);
-    if (i + 3 > j) break;
-    mgs_step<G, U>(n, i + 3, j, w, b3, V, ldv, H, ldh, sh);
+  double B[D][G];
+#pragma unroll
+  for (int d = 0; d < D; ++d) load_col<G>(B[d], V, ldv, min(d, j), rc);
+#pragma unroll
+  for (int i = 0; i < JU; ++i) {
+    mgs_step<G, U>(n, i, j, w, B[i % D], H, ldh, sh, lds_col, sHc);
+    if (i == j) goto orthogonal;
+    load_col<G>(B[i % D], V, ldv, min(i + D, j), rc);
   }
+  for (int i = JU; i <= j; ++i) {
+    double Bt[G];
+    load_col<G>(Bt, V, ldv, i, rc);
+    mgs_step<G, U>(n, i, j, w, Bt, H, ldh, sh, lds_col, sHc);
+  }
+orthogonal:
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < G; ++t) acc = __fma_rn(w[t], w[t], acc);
@@ -118,17 +142,18 @@ __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restric
   const int pb = (j + 1) & 1;
   if (lane == 0) sh[pb][wv] = acc;
   __syncthreads();
-  double nn = 0.0;
-#pragma unroll
-  for (int q = 0; q < GNT / 64; ++q) nn = __dadd_rn(nn, sh[pb][q]);
-  const double hn = sqrt(nn);
+  const double hn = sqrt(sum16_lanes(sh[pb]));
   if (tid == 0) {
-    double* hc = H + (size_t)j * ldh;
+    // rotate the new column by the previous Givens rotations, then a new rotation
+    // zeroes h_{j+1,j}; g is rotated and the stopping test taken
+    double* hc = lds_col ? sHc : H + (size_t)j * ldh;
+    const double* cc = lds_col ? sCs : cs;
+    const double* ss = lds_col ? sSn : sn;
     hc[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
       const double a = hc[i], b = hc[i + 1];
-      hc[i] = __dadd_rn(__dmul_rn(cs[i], a), __dmul_rn(sn[i], b));
-      hc[i + 1] = __dadd_rn(__dmul_rn(-sn[i], a), __dmul_rn(cs[i], b));
+      hc[i] = __dadd_rn(__dmul_rn(cc[i], a), __dmul_rn(ss[i], b));
+      hc[i + 1] = __dadd_rn(__dmul_rn(-ss[i], a), __dmul_rn(cc[i], b));
     }
     const double a = hc[j], b = hc[j + 1];
     const double r = hypot(a, b);
@@ -137,13 +162,16 @@ __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restric
     cs[j] = c; sn[j] = s;
     hc[j] = r;
     hc[j + 1] = 0.0;
-    const double gj = g[j];
     g[j + 1] = __dmul_rn(-s, gj);
     g[j] = __dmul_rn(c, gj);
     const double e = fabs(g[j + 1]);
-    const bool stop = !__builtin_isfinite(g[j + 1]) || e <= tau * (*beta0) || hn == 0.0;
+    const bool stop = !__builtin_isfinite(g[j + 1]) || e <= tau * b0 || hn == 0.0;
     st->jcount = j + 1;
     st->done = stop ? 1 : 0;
+  }
+  if (lds_col) {
+    __syncthreads();
+    for (int t = tid; t <= j + 1; t += GNT) H[(size_t)j * ldh + t] = sHc[t];
   }
   double* vnx = V + (size_t)(j + 1) * ldv;
 #pragma unroll
@@ -156,11 +184,12 @@ __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restric
 template <int G>
 static void launch_arnoldi_g(hipStream_t s, int n, int j, double* V, int ldv, const double* w, double* H, int ldh,
                              double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
+  constexpr int D = G <= 4 ? 8 : 4;   // vectors in flight, within the register budget of 1024-thread groups
   switch (u) {
-    case P_FP16: k_arnoldi<G, P_FP16><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    case P_BF16: k_arnoldi<G, P_BF16><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    case P_FP32: k_arnoldi<G, P_FP32><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    default: k_arnoldi<G, P_FP64><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    case P_FP16: k_arnoldi<G, P_FP16, D><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    case P_BF16: k_arnoldi<G, P_BF16, D><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    case P_FP32: k_arnoldi<G, P_FP32, D><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    default: k_arnoldi<G, P_FP64, D><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
   }
 }
 

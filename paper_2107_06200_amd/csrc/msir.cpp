@@ -155,13 +155,16 @@ int GmresOp::apply_solve(Ctx& c, const double* t, const int* skip, double* out, 
 }
 
 int GmresOp::apply_full(Ctx& c, const double* v, double* out, const int* skip) const {
-  int rc = matvec(c, n, A, lda, Au, n, v, p, tmp_hi, tmp_lo, skip);
-  if (rc) return rc;
   if (Xinv) {
-    rc = trgemv(c, n, inv_prec, Xinv, 1, tmp_hi, perm, R, 1.0, nullptr, p, tmp2, skip);
+    // A v is written already permuted and row-scaled (P R fl_p(A v)), the input of L^{-1}
+    int rc = matvec(c, n, A, lda, Au, n, v, p, tmp_hi, tmp_lo, skip, perm, R);
+    if (rc) return rc;
+    rc = trgemv(c, n, inv_prec, Xinv, 1, tmp_hi, nullptr, nullptr, 1.0, nullptr, p, tmp2, skip);
     if (rc) return rc;
     return trgemv(c, n, inv_prec, Yinv, 2, tmp2, nullptr, nullptr, mu, S, u, out, skip);
   }
+  int rc = matvec(c, n, A, lda, Au, n, v, p, tmp_hi, tmp_lo, skip);
+  if (rc) return rc;
   TrsvArgs a;
   a.n = n; a.prec = prec; a.W = W; a.ldw = ldw; a.perm = perm; a.rinv = rinv; a.R = R; a.S = S; a.mu = mu;
   a.comp = p; a.mode = mode; a.t_hi = tmp_hi; a.t_lo = (p == P_DD) ? tmp_lo : nullptr; a.y_hi = out;
@@ -595,6 +598,19 @@ int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, cons
   rc = trsv_check(h->c, &terr);
   if (rc) return rc;
   return terr ? MSIR_ERR_TIMEOUT : 0;
+}
+
+int msir_round(msir_handle* h, int n, msir_prec p, const double* dx, double* dy) {
+  if (!h) return -1;
+  if (n < 0) return MSIR_ERR_SIZE;
+  if (p < MSIR_FP16 || p > MSIR_DD) return -3;
+  if (n == 0) return 0;
+  if (!dx || !dy) return -4;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  int rc = round_vec(h->c, n, dx, dy, p);
+  if (rc) return rc;
+  HIP_CHECK(hipStreamSynchronize(h->c.stream));
+  return 0;
 }
 
 int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double* dx, const double* db,

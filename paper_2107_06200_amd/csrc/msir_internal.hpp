@@ -71,8 +71,9 @@ int scaling(Ctx& c, int n, const double* A, int lda, int prec, int rows, double*
 // residual when want_true (or ur == DD); rhat = fl_u(r / s_dev[0]) if rhat != null.
 int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
              double* rhat, double* s_dev, bool want_true);
+// y = fl_p(A v); with operm (p != DD) y[i] = oR[q] * fl_p(A v)_q, q = operm[i].
 int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
-           double* y_hi, double* y_lo, const int* skip);
+           double* y_hi, double* y_lo, const int* skip, const int* operm = nullptr, const double* oR = nullptr);
 int update_into(Ctx& c, int n, const double* x, double* xnew, const double* d, const double* s_dev, int ux,
                 double* mon_dev);
 int norms(Ctx& c, int n, const double* A, int lda, const double* b, double* out_dev);
@@ -137,8 +138,10 @@ GemvPlan gemv_plan(int n, int tri);
 int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const double* x,
                   const int* perm, const double* R, int mode, double* ph, double* pl, double* px, const int* skip);
 // y = round_p(oscale * folded partials), oscale_i = S ? mu S[i] : 1; p == DD writes y_hi/y_lo.
+// operm (p != DD): slot i receives oR[q] * (the value of row q = operm[i]) (oR may be null).
 int gemv_finish(Ctx& c, const GemvPlan& g, int n, const double* ph, const double* pl, double mu, const double* S,
-                int p, double* y_hi, double* y_lo, const int* skip);
+                int p, double* y_hi, double* y_lo, const int* skip, const int* operm = nullptr,
+                const double* oR = nullptr);
 int diag_block_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* dinv);
 size_t diag_inv_doubles(int n);
 

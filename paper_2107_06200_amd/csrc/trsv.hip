@@ -87,13 +87,25 @@ __device__ __forceinline__ bool mb_load(const unsigned long long* p, unsigned ep
 
 // Every lane of the wave with `need` reads row `row` of the mailbox; the wave
 // polls until all of them hold this launch's words (lanes without `need` get 0).
+// While the block is not yet published the wave polls a single word (that of
+// `probe`, a row of the same block, written by the same store instructions), so
+// waiting workgroups put one request per poll on the memory system, not one per
+// lane.
 template <bool DD>
-__device__ __forceinline__ void mb_get(const unsigned long long* mb, int row, bool need, unsigned epoch,
+__device__ __forceinline__ void mb_get(const unsigned long long* mb, int row, bool need, int probe, unsigned epoch,
                                        unsigned* err, double& h, double& l) {
   constexpr int NW = DD ? 4 : 2;
   h = 0.0;
   l = 0.0;
   long spins = 0;
+  const unsigned long long* pw = mb + (size_t)probe * NW + 1;
+  while ((unsigned)(__hip_atomic_load(pw, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >> 32) != epoch) {
+    __builtin_amdgcn_s_sleep(1);
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(err, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+  }
   for (;;) {
     bool ok = true;
     if (need) {
@@ -159,7 +171,7 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
     for (int q = 0; q < 16; ++q) lv[q] = (blk > 0 && rv) ? Store<P>::to_d(W[(size_t)(16 * gu + q) * a.ldw + grow]) : 0.0;
     for (int j = 0; j < blk; ++j) {
       double yh, yl;
-      mb_get<DD>(a.mbf, j * TB + lr, true, a.epoch, a.err, yh, yl);
+      mb_get<DD>(a.mbf, j * TB + lr, true, j * TB + TB - 1, a.epoch, a.err, yh, yl);
       double ln[16];
       const int cn = (j + 1) * TB + 16 * gu;
 #pragma unroll
@@ -190,7 +202,7 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
     }
     for (int j = nblk - 1; j > blk; --j) {
       double xh, xl;
-      mb_get<DD>(a.mbb, j * TB + lr, j * TB + lr < a.n, a.epoch, a.err, xh, xl);
+      mb_get<DD>(a.mbb, j * TB + lr, j * TB + lr < a.n, min(a.n, j * TB + TB) - 1, a.epoch, a.err, xh, xl);
       double un[16];
       const int cn = (j - 1) * TB + 16 * gu;
 #pragma unroll
@@ -235,7 +247,7 @@ __global__ __launch_bounds__(TNT) void k_trsv(TrsvK a) {
       else ah = round_c<C>(ah);
     }
   } else {
-    mb_get<DD>(a.mbf, grow, rv, a.epoch, a.err, ah, al);
+    mb_get<DD>(a.mbf, grow, rv, r0 + rows - 1, a.epoch, a.err, ah, al);
   }
   if (rv) {
     if (!DD) ah = __dsub_rn(ah, th);

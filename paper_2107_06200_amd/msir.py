@@ -54,7 +54,7 @@ class Result(ctypes.Structure):
 
 SYMBOLS = ["msir_create", "msir_destroy", "msir_params_default", "msir_nb_auto", "msir_workspace_bytes",
            "msir_status_string", "msir_solve", "msir_solve_multi", "msir_solve_batched", "msir_convert",
-           "msir_scaling", "msir_getrf", "msir_getrs", "msir_residual", "msir_gmres", "msir_backward_error",
+           "msir_scaling", "msir_getrf", "msir_getrs", "msir_round", "msir_residual", "msir_gmres", "msir_backward_error",
            "msir_timing", "msir_timing_get"]
 
 _P = ctypes.c_void_p
@@ -77,6 +77,7 @@ _SIG = {
     "msir_scaling": (_I, [_P, _I, _P, _I, _I, _I, _P, _P, _P]),
     "msir_getrf": (_I, [_P, _I, _I, _P, _I, _I, _I, _P, ctypes.POINTER(_I)]),
     "msir_getrs": (_I, [_P, _I, _I, _P, _I, _P, _P, _P, _D, _I, _I, _P, _P]),
+    "msir_round": (_I, [_P, _I, _I, _P, _P]),
     "msir_residual": (_I, [_P, _I, _P, _I, _P, _P, _I, _I, _P, ctypes.POINTER(_D)]),
     "msir_gmres": (_I, [_P, _I, _P, _I, _I, _P, _I, _P, _P, _P, _D, _P, _I, _I, _D, _D, _I, _P,
                         ctypes.POINTER(_I)]),
@@ -281,6 +282,15 @@ def getrs(h, W, fmt, ipiv, t, comp, R=None, S=None, mu=1.0, mode=0):
     y = torch.empty(2 * n if c == 4 else n, dtype=torch.float64, device=W.device)
     _check(lib().msir_getrs(h.h, n, _prec(fmt), _ptr(W), _ld(W), _ptr(ipiv), _ptr(R), _ptr(S), float(mu), c, mode,
                             _ptr(t), _ptr(y)), "msir_getrs")
+    return y
+
+
+def round_values(h, x, fmt):
+    """fl_fmt(x) for a float64 device vector (new tensor)."""
+    import torch
+    assert x.dtype == torch.float64 and x.is_contiguous()
+    y = torch.empty_like(x)
+    _check(lib().msir_round(h.h, x.numel(), _prec(fmt), _ptr(x), _ptr(y)), "msir_round")
     return y
 
 

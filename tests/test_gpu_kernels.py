@@ -101,6 +101,37 @@ def test_scaling_and_scaled_convert_bitexact(M, h, rows):
     np.testing.assert_array_equal(got, F.round_to(OSC.apply(A, Ro, So, muo), "fp16"))
 
 
+@pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp32"])
+def test_round_values_bitexact(M, h, fmt):
+    # fl_fmt(x) as every refinement kernel applies it, against the oracle's rounding:
+    # random magnitudes over the whole range plus ties, the subnormal range, the
+    # overflow threshold and the special values
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(40000) * np.exp2(rng.uniform(-160, 140, 40000))
+    t = {"fp16": (11, -14, 15), "bf16": (8, -126, 127), "fp32": (24, -126, 127)}[fmt]
+    p, emin, emax = t
+    xmax = (2.0 - 2.0 ** (1 - p)) * 2.0 ** emax
+    q = 2.0 ** (emin - p + 1)
+    edge = [0.0, -0.0, np.inf, -np.inf, xmax, -xmax, xmax * (1 + 2.0 ** -p), xmax * (1 + 2.0 ** -p) * (1 - 2.0 ** -40),
+            1.0 + 2.0 ** -p, 1.0 + 3 * 2.0 ** -p, 1.0 + 2.0 ** -p + 2.0 ** -50, q, q / 2, 3 * q / 2, q / 2 * (1 + 2.0 ** -30),
+            2.0 ** emin, 2.0 ** emin - q / 2, 1e-300, -1e-300, 1e300, 5e-324]
+    x[: len(edge)] = edge
+    x[len(edge): 2 * len(edge)] = -np.array(edge)
+    k = np.arange(4000)   # exact ties across binades
+    x[100:4100] = (2 * rng.integers(1, 2 ** p, 4000) + 1) * 2.0 ** (rng.integers(emin - p, emax - p, 4000) - 1)
+    got = M.round_values(h, tdev(x), fmt).cpu().numpy()
+    want = F.round_to(x, fmt)
+    np.testing.assert_array_equal(got, want)
+    np.testing.assert_array_equal(np.signbit(got), np.signbit(want))
+
+
+def test_round_values_nan(M, h):
+    x = np.array([np.nan, 1.0, -np.nan])
+    for fmt in ("fp16", "bf16", "fp32", "fp64"):
+        got = M.round_values(h, tdev(x), fmt).cpu().numpy()
+        assert np.isnan(got[0]) and got[1] == 1.0 and np.isnan(got[2])
+
+
 # ------------------------------------------------------------------ LU
 @pytest.mark.parametrize("fmt", ["fp16", "bf16", "fp32", "fp64"])
 @pytest.mark.parametrize("n", [1, 5, 32])
