@@ -258,12 +258,14 @@ typedef enum {
     MSIR_T_SWAP = 1,     /* row interchanges + U12 triangular solve              */
     MSIR_T_GEMM = 2,     /* LU trailing update (matrix cores)                    */
     MSIR_T_TRSV = 3,     /* forward + backward triangular solve                  */
-    MSIR_T_MATVEC = 4,   /* A v inside GMRES                                     */
+    MSIR_T_MATVEC = 4,   /* A v inside GMRES, fp32 copy of A (partials + fold)    */
     MSIR_T_RESID = 5,    /* residual b - A x and its scaling                     */
     MSIR_T_ARNOLDI = 6,  /* modified Gram-Schmidt + Givens                       */
-    MSIR_T_TRGEMV = 7,   /* M^{-1} v through the explicit triangular inverses    */
+    MSIR_T_TRGEMV = 7,   /* one triangular product with an fp32 inverse factor   */
     MSIR_T_OTHER = 8,
-    MSIR_T_COUNT = 9
+    MSIR_T_MATVEC64 = 9, /* A v inside GMRES with the float64 A (fp64 or dd)      */
+    MSIR_T_TRGEMV64 = 10,/* one triangular product with an fp64 inverse factor   */
+    MSIR_T_COUNT = 11
 } msir_timer;
 /* enable != 0: start timing (counters reset); 0: stop.                          */
 MSIR_API int msir_timing(msir_handle* h, int enable);

@@ -260,7 +260,7 @@ int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, c
   double* ph = c.ws_part_hi(g.ns * (size_t)n);
   double* pl = c.ws_part_lo(g.ns * (size_t)n);
   if (!ph || !pl) return MSIR_ERR_ALLOC;
-  const int _slot = c.tbegin(MSIR_T_MATVEC);
+  const int _slot = c.tbegin(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
   int rc;
   if (p == P_FP32) rc = gemv_partials(c, g, n, P_FP32, Au, ldau, v, nullptr, nullptr, 0, ph, pl, nullptr, skip);
   else rc = gemv_partials(c, g, n, P_FP64, A, lda, v, nullptr, nullptr, p == P_DD ? 1 : 0, ph, pl, nullptr, skip);

@@ -204,7 +204,7 @@ int trgemv(Ctx& c, int n, int store_prec, const void* T, int tri, const double* 
   const GemvPlan g = gemv_plan(n, tri);
   double* part = (double*)c.grow(c.tr_part, (size_t)g.ns * n * sizeof(double));
   if (!part) return MSIR_ERR_ALLOC;
-  const int slot = c.tbegin(MSIR_T_TRGEMV);
+  const int slot = c.tbegin(store_prec == P_FP32 ? MSIR_T_TRGEMV : MSIR_T_TRGEMV64);
   int rc = gemv_partials(c, g, n, store_prec, T, n, x, perm, R, 0, part, nullptr, nullptr, skip);
   if (!rc) rc = gemv_finish(c, g, n, part, nullptr, mu, S, p, y, nullptr, skip);
   c.tend(slot);
