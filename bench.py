@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=None, help="override the order (testing only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lu-update", choices=["mfma", "fma"], default="mfma",
+                    help="trailing update of the fp16/bf16 LU: matrix cores or fp32 FMA chains")
     return ap.parse_args()
 
 
@@ -130,7 +132,7 @@ def main():
     h = M.Handle(0)
     At = M.colmajor(torch.from_numpy(np.asfortranarray(A)).to(dev))
     bt = torch.from_numpy(b).to(dev)
-    P = M.params(**cfg["params"])
+    P = M.params(lu_update=args.lu_update, **cfg["params"])
     x = torch.empty(n, dtype=torch.float64, device=dev)
     res = hist = None
     for _ in range(args.warmup):
