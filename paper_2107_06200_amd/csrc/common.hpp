@@ -229,21 +229,24 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum of the 16 per-wave partials p[0..15] (LDS), uniform over the calling wave:
-// lane k < 16 reads p[k] and four DPP steps fold them (fixed order).  Only 128 bytes
-// of LDS are read per wave, instead of every lane reading all sixteen values.
-__device__ __forceinline__ double sum16_lanes(const double* p) {
+// Sum of the W (8 or 16) per-wave partials p[0..W-1] (LDS), uniform over the calling
+// wave: lane k < W reads p[k] and DPP steps fold them in a fixed order.  Only 8W bytes
+// of LDS are read per wave, instead of every lane reading all W values.
+template <int W>
+__device__ __forceinline__ double sum_lanes(const double* p) {
+  static_assert(W == 8 || W == 16, "8 or 16 partials");
   const int lane = threadIdx.x & 63;
-  double v = lane < 16 ? p[lane] : 0.0;
+  double v = lane < W ? p[lane] : 0.0;
   v = __dadd_rn(v, dpp_d<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
   v = __dadd_rn(v, dpp_d<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
-  v = __dadd_rn(v, dpp_d<0x141, 0xF>(v));   // row_half_mirror
-  v = __dadd_rn(v, dpp_d<0x140, 0xF>(v));   // row_mirror: lanes 0..15 hold the total
+  v = __dadd_rn(v, dpp_d<0x141, 0xF>(v));   // row_half_mirror: lanes 0..7 hold the sum of 0..7
+  if constexpr (W == 16) v = __dadd_rn(v, dpp_d<0x140, 0xF>(v));   // row_mirror
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 0);
   const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 0);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
+__device__ __forceinline__ double sum16_lanes(const double* p) { return sum_lanes<16>(p); }
 
 // Ordered folds of strided partial sums p[s * stride] for s in [s_lo, s_hi): the
 // loads are issued sixteen at a time, the additions stay in slice order.

@@ -91,20 +91,41 @@ __device__ __forceinline__ void slice_range(int n, int rb, int s, int chunk, int
 
 // part_hi[s * n + row] (and part_lo, part_x by MODE) = sum over slice s of T[row, j] xin[j],
 // xin[j] = perm ? R[perm[j]] x[perm[j]] (R may be null) : x[j].
-// WV waves per workgroup (column groups): 16 for fp32 matrices and the double-double
-// modes, 8 for plain float64 products (whose eight 32-byte columns in flight per
-// lane need the larger register budget of a 512-thread workgroup).
+// WV waves per workgroup (column groups).  Full products: 16 for fp32 and the
+// double-double modes, 8 for plain float64 (eight 32-byte columns in flight per lane
+// need the register budget of a 512-thread workgroup).  Triangular products: 8, with
+// four float64 columns in flight, so that two workgroups fit on a compute unit and
+// every busy (row block, slice) pair of the compact grid is resident at once; a
+// second dispatch round would double the time of these short launches.
 template <typename TA, int MODE, int TRI, int WV>
-__global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ A, int lda, bool aligned,
-                                               const double* __restrict__ x, const int* __restrict__ perm,
-                                               const double* __restrict__ R, int chunk,
-                                               double* __restrict__ p_hi, double* __restrict__ p_lo,
+__global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ A, int lda, bool aligned, GemvIn in,
+                                               int chunk, double* __restrict__ p_hi, double* __restrict__ p_lo,
                                                double* __restrict__ p_x, const int* __restrict__ skip) {
   if (skip && *skip) return;
-  const int rb = blockIdx.x, s = blockIdx.y;
+  int rb, s;
+  if (TRI == 0) {
+    rb = blockIdx.x;
+    s = blockIdx.y;
+  } else {
+    // compact 1-D grid over the (row block, slice) pairs that meet the triangle, row
+    // block by row block: a short uniform walk over the row blocks finds this pair
+    const int ns = (n + chunk - 1) / chunk;
+    const int nrb = (n + GV_ROWS - 1) / GV_ROWS;
+    int id = blockIdx.x;
+    rb = 0;
+    for (;;) {
+      if (rb >= nrb) return;   // grid larger than the pair count: nothing to do
+      const int rlo = rb * GV_ROWS;
+      const int s_lo = (TRI == 2) ? rlo / chunk : 0;
+      const int s_hi = (TRI == 1) ? (min(n, rlo + GV_ROWS) + chunk - 1) / chunk : ns;
+      if (id < s_hi - s_lo) { s = s_lo + id; break; }
+      id -= s_hi - s_lo;
+      ++rb;
+    }
+  }
   int j0, j1;
   slice_range<TRI>(n, rb, s, chunk, j0, j1);
-  if (j0 >= j1) return;   // uniform over the workgroup; the finish kernel skips this slice
+  if (j0 >= j1) return;   // (does not happen with the compact grid)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -114,12 +135,33 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   __shared__ double lds[NB * GV_WAVES * GV_ROWS];   // x slice first, then the wave sums
   double* sx = lds;
   const int len = j1 - j0;
-  // 1. loads of this workgroup's x slice (clamped indices, issued unconditionally)
+  // 1. loads of this workgroup's x slice.  Plain input: clamped indices, issued
+  // unconditionally (optionally gathered and scaled).  Partials of the producing
+  // product: `sub` threads per element each fold a contiguous run of the producer's
+  // slices (issued before the matrix loads), combined in run order below.
+  __shared__ double ssub[GV_T];
   double xs[XPT];
+  const int sub = in.xpart ? min(8, max(1, GV_T / len)) : 1;
+  if (!in.xpart) {
 #pragma unroll
-  for (int q = 0; q < XPT; ++q) {
-    const int jj = j0 + min(tid + q * GV_T, len - 1);
-    if (perm) { const int pq = perm[jj]; xs[q] = R ? R[pq] * x[pq] : x[pq]; } else xs[q] = x[jj];
+    for (int q = 0; q < XPT; ++q) {
+      const int jj = j0 + min(tid + q * GV_T, len - 1);
+      if (in.perm) {
+        const int pq = in.perm[jj];
+        xs[q] = in.R ? in.R[pq] * in.x[pq] : in.x[pq];
+      } else {
+        xs[q] = in.x[jj];
+      }
+    }
+  } else if (tid < sub * len) {
+    const int e = tid % len, k = tid / len;
+    const int jj = j0 + e;
+    const int rbj = jj / GV_ROWS;
+    const int s_lo = (in.xtri == 2) ? (rbj * GV_ROWS) / in.xchunk : 0;
+    const int s_hi = (in.xtri == 1) ? (min(n, (rbj + 1) * GV_ROWS) + in.xchunk - 1) / in.xchunk : in.xns;
+    const int q = (s_hi - s_lo + sub - 1) / sub;
+    const int a0 = min(s_hi, s_lo + k * q), a1 = min(s_hi, a0 + q);
+    xs[0] = fold_sum(in.xpart + jj, (size_t)n, a0, a1);
   }
   // 2. the first batch of matrix columns, in flight before the slice is needed
   const int rlo = rb * GV_ROWS;
@@ -127,7 +169,7 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   const int valid = max(0, min(4, n - r0));
   const bool vec = aligned && valid == 4;
   const TA* a = A + min(r0, n - 1);
-  constexpr int UNR = (sizeof(TA) == 4 || MODE == 0) ? 8 : 4;   // columns in flight per lane
+  constexpr int UNR = (sizeof(TA) == 4 || (MODE == 0 && TRI == 0)) ? 8 : 4;   // columns in flight per lane
   static_assert(UNR * GV_WAVES <= GV_BATCH && GV_BATCH % (UNR * GV_WAVES) == 0, "slices must be whole batches");
   TA v[UNR][4];
   int j = j0 + w;
@@ -136,9 +178,21 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
     for (int u = 0; u < UNR; ++u) load4<TA>(a + (size_t)min(j + u * GV_WAVES, j1 - 1) * lda, vec, valid, v[u]);
   }
   // 3. slice into LDS
+  if (!in.xpart) {
 #pragma unroll
-  for (int q = 0; q < XPT; ++q)
-    if (tid + q * GV_T < len) sx[tid + q * GV_T] = xs[q];
+    for (int q = 0; q < XPT; ++q)
+      if (tid + q * GV_T < len) sx[tid + q * GV_T] = xs[q];
+  } else {
+    if (tid < sub * len) ssub[tid] = xs[0];
+    __syncthreads();
+    if (tid < len) {
+      double t = ssub[tid];
+      for (int k = 1; k < sub; ++k) t = __dadd_rn(t, ssub[k * len + tid]);
+      if (in.xround >= 0) t = round_to(t, in.xround);
+      if (in.xscale) t = in.xscale[j0 + tid] * t;
+      sx[tid] = t;
+    }
+  }
   __syncthreads();
   // 4. batches of UNR columns per wave: accumulate the batch (columns past the slice or
   // outside the triangle contribute exact zeros), then load the next one
@@ -177,8 +231,9 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
       if (MODE == 0) th = __dadd_rn(th, sh[q * GV_ROWS + tid]);
       else dd_add(th, tl, sh[q * GV_ROWS + tid], sl[q * GV_ROWS + tid], th, tl);
     }
-    p_hi[(size_t)s * n + rlo + tid] = th;
-    if (MODE != 0) p_lo[(size_t)s * n + rlo + tid] = tl;
+    const int orow = in.prow ? in.prow[rlo + tid] : rlo + tid;
+    p_hi[(size_t)s * n + orow] = th;
+    if (MODE != 0) p_lo[(size_t)s * n + orow] = tl;
   }
   if (MODE == 2) {
     __syncthreads();
@@ -188,7 +243,7 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
     if (tid < GV_ROWS && rlo + tid < n) {
       double tx = sh[tid];
       for (int q = 1; q < GV_WAVES; ++q) tx = __dadd_rn(tx, sh[q * GV_ROWS + tid]);
-      p_x[(size_t)s * n + rlo + tid] = tx;
+      p_x[(size_t)s * n + (in.prow ? in.prow[rlo + tid] : rlo + tid)] = tx;
     }
   }
 }
@@ -247,39 +302,64 @@ GemvPlan gemv_plan(int n, int tri) {
   if (chunk < 1) chunk = 1;
   g.chunk = (int)chunk;
   g.ns = n > 0 ? (int)((n + chunk - 1) / chunk) : 1;
+  // busy (row block, slice) pairs: the compact grid of a triangular product
+  g.nwg = 0;
+  for (int r = 0; r < g.rb; ++r) {
+    const int rlo = r * GV_ROWS, rhi = n < rlo + GV_ROWS ? n : rlo + GV_ROWS;
+    const int s_lo = tri == 2 ? rlo / g.chunk : 0;
+    const int s_hi = tri == 1 ? (rhi + g.chunk - 1) / g.chunk : g.ns;
+    g.nwg += s_hi - s_lo;
+  }
   return g;
 }
 
 template <typename TA, int MODE>
-static void launch_gemv(Ctx& c, const GemvPlan& g, int n, const TA* A, int lda, const double* x, const int* perm,
-                        const double* R, double* ph, double* pl, double* px, const int* skip) {
+static void launch_gemv(Ctx& c, const GemvPlan& g, int n, const TA* A, int lda, const GemvIn& in, double* ph,
+                        double* pl, double* px, const int* skip) {
   constexpr int WV = (sizeof(TA) == 8 && MODE == 0) ? 8 : 16;
+  constexpr int WVT = (MODE == 0) ? 8 : 16;
   const bool aligned = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
-  dim3 grid(g.rb, g.ns);
   if (g.tri == 0)
-    k_gemv<TA, MODE, 0, WV><<<grid, 64 * WV, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
+    k_gemv<TA, MODE, 0, WV><<<dim3(g.rb, g.ns), 64 * WV, 0, c.stream>>>(n, A, lda, aligned, in, g.chunk, ph, pl, px,
+                                                                        skip);
   else if (g.tri == 1)
-    k_gemv<TA, MODE, 1, WV><<<grid, 64 * WV, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
+    k_gemv<TA, MODE, 1, WVT><<<g.nwg, 64 * WVT, 0, c.stream>>>(n, A, lda, aligned, in, g.chunk, ph, pl, px, skip);
   else
-    k_gemv<TA, MODE, 2, WV><<<grid, 64 * WV, 0, c.stream>>>(n, A, lda, aligned, x, perm, R, g.chunk, ph, pl, px, skip);
+    k_gemv<TA, MODE, 2, WVT><<<g.nwg, 64 * WVT, 0, c.stream>>>(n, A, lda, aligned, in, g.chunk, ph, pl, px, skip);
 }
 
-int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const double* x,
-                  const int* perm, const double* R, int mode, double* ph, double* pl, double* px, const int* skip) {
+int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const GemvIn& in, int mode,
+                  double* ph, double* pl, double* px, const int* skip) {
   if (n <= 0) return 0;
+  if (in.xpart) {
+    // fold-mode staging needs a thread per slice element: workgroup size as launched
+    int nt;
+    if (g.tri == 0) nt = (a_prec == P_FP64 && mode == 0) ? 512 : 1024;
+    else nt = (mode == 0) ? 512 : 1024;
+    if (g.chunk > nt || in.xchunk < 1 || in.xns < 1) return -3;
+  }
   if (a_prec == P_FP32) {
     if (mode != 0) return -3;
-    launch_gemv<float, 0>(c, g, n, (const float*)A, lda, x, perm, R, ph, pl, px, skip);
+    launch_gemv<float, 0>(c, g, n, (const float*)A, lda, in, ph, pl, px, skip);
   } else if (a_prec == P_FP64) {
     const double* Ad = (const double*)A;
-    if (mode == 0) launch_gemv<double, 0>(c, g, n, Ad, lda, x, perm, R, ph, pl, px, skip);
-    else if (mode == 1) launch_gemv<double, 1>(c, g, n, Ad, lda, x, perm, R, ph, pl, px, skip);
-    else launch_gemv<double, 2>(c, g, n, Ad, lda, x, perm, R, ph, pl, px, skip);
+    if (mode == 0) launch_gemv<double, 0>(c, g, n, Ad, lda, in, ph, pl, px, skip);
+    else if (mode == 1) launch_gemv<double, 1>(c, g, n, Ad, lda, in, ph, pl, px, skip);
+    else launch_gemv<double, 2>(c, g, n, Ad, lda, in, ph, pl, px, skip);
   } else {
     return -3;
   }
   HIP_CHECK(hipGetLastError());
   return 0;
+}
+
+int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const double* x,
+                  const int* perm, const double* R, int mode, double* ph, double* pl, double* px, const int* skip) {
+  GemvIn in;
+  in.x = x;
+  in.perm = perm;
+  in.R = R;
+  return gemv_partials(c, g, n, a_prec, A, lda, in, mode, ph, pl, px, skip);
 }
 
 int gemv_finish(Ctx& c, const GemvPlan& g, int n, const double* ph, const double* pl, double mu, const double* S,

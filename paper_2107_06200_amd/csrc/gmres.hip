@@ -20,6 +20,11 @@
 namespace msir {
 
 constexpr int GNT = 1024;
+// Arnoldi workgroup size: 512 threads up to n = 4096, so that the per-inner-product
+// work every wave repeats (wave reduction, barrier, fold, address arithmetic) is
+// issued by 8 waves instead of 16 while the element work per compute unit is the
+// same (the SIMDs are issue-bound here); 1024 threads beyond, where 512 threads would
+// need more registers than a wave has.
 
 // beta = ||resid||_2; g[0] = beta; V0 = fl_u(resid / beta); status reset
 __global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __restrict__ resid, double* __restrict__ V0,
@@ -44,9 +49,9 @@ __global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __rest
 // barrier), w <- fl_u(w - h B).  h goes to the LDS copy of the Hessenberg column
 // (sHc, when the column fits) or straight to H (stored by every lane, same value,
 // so that all waves issue the same memory operations).
-template <int G, int U>
+template <int G, int U, int NT>
 __device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], const double (&B)[G],
-                                         double* __restrict__ H, int ldh, double (*sh)[GNT / 64], bool lds_col,
+                                         double* __restrict__ H, int ldh, double (*sh)[NT / 64], bool lds_col,
                                          double* sHc) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
@@ -56,11 +61,11 @@ __device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], co
   acc = wave_sum_dpp(acc);
   if (lane == 0) sh[i & 1][wv] = acc;
   __syncthreads();
-  const double h = sum16_lanes(sh[i & 1]);
+  const double h = sum_lanes<NT / 64>(sh[i & 1]);
 #pragma unroll
   for (int t = 0; t < G; ++t) {
     const double nw = round_c<U>(__dsub_rn(w[t], __dmul_rn(h, B[t])));
-    w[t] = (tid + t * GNT < n) ? nw : 0.0;
+    w[t] = (tid + t * NT < n) ? nw : 0.0;
   }
   if (lds_col) {
     if (tid == 0) sHc[i] = h;
@@ -82,23 +87,23 @@ __device__ __forceinline__ void load_col(double (&B)[G], const double* __restric
 // modified Gram-Schmidt, h_{j+1,j} = ||w||_2, the new Hessenberg column is rotated
 // by the previous Givens rotations and a new rotation zeroes h_{j+1,j}; g is
 // rotated and the stopping test |g_{j+1}| <= tau beta0 is taken.  G values per
-// thread (n <= G * GNT), U the working precision.  The first JU inner products are
+// thread (n <= G * NT), U the working precision.  The first JU inner products are
 // straight-line code with a ring of D basis vectors in flight (the refill of a slot
 // is issued right after the slot is consumed), so the loads of v_{i+D} overlap D
 // inner products; beyond JU a rolled loop loads each vector when it is needed.
 constexpr int JU = 64;
 constexpr int JL = 512;   // Hessenberg columns up to this length are rotated in LDS
-template <int G, int U, int D>
-__global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restrict__ V, int ldv,
+template <int G, int U, int D, int NT>
+__global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict__ V, int ldv,
                                                  const double* __restrict__ w_in, double* __restrict__ H, int ldh,
                                                  double* __restrict__ cs, double* __restrict__ sn,
                                                  double* __restrict__ g, const double* __restrict__ beta0, double tau,
                                                  GStatus* st) {
-  static_assert(GNT / 64 == 16, "sum16_lanes folds sixteen wave partials");
+  static_assert(NT == 512 || NT == 1024, "8 or 16 wave partials");
   if (st->done) return;
   // per-wave partial sums, double-buffered by the parity of the inner-product index
   // so that one barrier per inner product suffices
-  __shared__ double sh[2][GNT / 64];
+  __shared__ double sh[2][NT / 64];
   // the Hessenberg column and the previous rotations, staged in LDS so that the
   // serial rotation sweep below runs on LDS, not on global-memory round trips
   __shared__ double sHc[JL], sCs[JL], sSn[JL];
@@ -115,7 +120,7 @@ __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restric
   double w[G];
 #pragma unroll
   for (int t = 0; t < G; ++t) {
-    const int r = tid + t * GNT;
+    const int r = tid + t * NT;
     rc[t] = min(r, n - 1);
     const double v = w_in[rc[t]];
     w[t] = r < n ? v : 0.0;
@@ -125,14 +130,14 @@ __global__ __launch_bounds__(GNT) void k_arnoldi(int n, int j, double* __restric
   for (int d = 0; d < D; ++d) load_col<G>(B[d], V, ldv, min(d, j), rc);
 #pragma unroll
   for (int i = 0; i < JU; ++i) {
-    mgs_step<G, U>(n, i, j, w, B[i % D], H, ldh, sh, lds_col, sHc);
+    mgs_step<G, U, NT>(n, i, j, w, B[i % D], H, ldh, sh, lds_col, sHc);
     if (i == j) goto orthogonal;
     load_col<G>(B[i % D], V, ldv, min(i + D, j), rc);
   }
   for (int i = JU; i <= j; ++i) {
     double Bt[G];
     load_col<G>(Bt, V, ldv, i, rc);
-    mgs_step<G, U>(n, i, j, w, Bt, H, ldh, sh, lds_col, sHc);
+    mgs_step<G, U, NT>(n, i, j, w, Bt, H, ldh, sh, lds_col, sHc);
   }
 orthogonal:
   double acc = 0.0;
@@ -142,7 +147,7 @@ orthogonal:
   const int pb = (j + 1) & 1;
   if (lane == 0) sh[pb][wv] = acc;
   __syncthreads();
-  const double hn = sqrt(sum16_lanes(sh[pb]));
+  const double hn = sqrt(sum_lanes<NT / 64>(sh[pb]));
   if (tid == 0) {
     // rotate the new column by the previous Givens rotations, then a new rotation
     // zeroes h_{j+1,j}; g is rotated and the stopping test taken
@@ -171,34 +176,35 @@ orthogonal:
   }
   if (lds_col) {
     __syncthreads();
-    for (int t = tid; t <= j + 1; t += GNT) H[(size_t)j * ldh + t] = sHc[t];
+    for (int t = tid; t <= j + 1; t += NT) H[(size_t)j * ldh + t] = sHc[t];
   }
   double* vnx = V + (size_t)(j + 1) * ldv;
 #pragma unroll
   for (int t = 0; t < G; ++t) {
-    const int r = tid + t * GNT;
+    const int r = tid + t * NT;
     if (r < n) vnx[r] = round_c<U>(w[t] / hn);
   }
 }
 
-template <int G>
+template <int G, int D, int NT>
 static void launch_arnoldi_g(hipStream_t s, int n, int j, double* V, int ldv, const double* w, double* H, int ldh,
                              double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
-  constexpr int D = G <= 4 ? 8 : 4;   // vectors in flight, within the register budget of 1024-thread groups
   switch (u) {
-    case P_FP16: k_arnoldi<G, P_FP16, D><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    case P_BF16: k_arnoldi<G, P_BF16, D><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    case P_FP32: k_arnoldi<G, P_FP32, D><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    default: k_arnoldi<G, P_FP64, D><<<1, GNT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    case P_FP16: k_arnoldi<G, P_FP16, D, NT><<<1, NT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    case P_BF16: k_arnoldi<G, P_BF16, D, NT><<<1, NT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    case P_FP32: k_arnoldi<G, P_FP32, D, NT><<<1, NT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
+    default: k_arnoldi<G, P_FP64, D, NT><<<1, NT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
   }
 }
 
+// values per thread G, basis vectors in flight D, threads NT (see above)
 static void launch_arnoldi(hipStream_t s, int n, int j, double* V, int ldv, const double* w, double* H, int ldh,
                            double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
-  if (n <= GNT) launch_arnoldi_g<1>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else if (n <= 2 * GNT) launch_arnoldi_g<2>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else if (n <= 4 * GNT) launch_arnoldi_g<4>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else launch_arnoldi_g<8>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  if (n <= 512) launch_arnoldi_g<1, 8, 512>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else if (n <= 1024) launch_arnoldi_g<2, 8, 512>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else if (n <= 2048) launch_arnoldi_g<4, 8, 512>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else if (n <= 4096) launch_arnoldi_g<4, 8, 1024>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else launch_arnoldi_g<8, 2, 1024>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
 }
 
 // y = R^{-1} g (upper triangular from the rotated Hessenberg), one wave,

@@ -32,6 +32,8 @@ struct GmresOp {
   const void* W;
   int ldw;
   const int* perm;
+  const int* pinv = nullptr;     // inverse permutation (operator through inverses)
+  const double* Rp = nullptr;    // R in pivot order (null: no row scaling)
   const double* rinv;
   const double* R;
   const double* S;

@@ -211,4 +211,48 @@ int trgemv(Ctx& c, int n, int store_prec, const void* T, int tri, const double* 
   return rc;
 }
 
+// GMRES operator through the inverses in four launches: A v partial sums written in
+// pivot order (row perm[j] at column j); X times (Rp fl_p(folded A v)); Y times
+// fl_p(folded X product); fl_u(mu S folded Y product).  Each product folds its
+// predecessor's partial sums while staging its input slice, so the intermediate
+// vectors never exist as separate launches.
+int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au, const double* v, const int* pinv,
+                 const double* Rp, int inv_prec, const void* X, const void* Y, double mu, const double* S, int u,
+                 double* out, const int* skip) {
+  if (p != P_FP32 && p != P_FP64) return -3;
+  const GemvPlan gm = gemv_plan(n, 0), gl = gemv_plan(n, 1), gu = gemv_plan(n, 2);
+  double* pa = c.ws_part_hi((size_t)(gm.ns > gu.ns ? gm.ns : gu.ns) * n);
+  double* pb = (double*)c.grow(c.tr_part, (size_t)gl.ns * n * sizeof(double));
+  if (!pa || !pb) return MSIR_ERR_ALLOC;
+  int rc;
+  {
+    GemvIn in;
+    in.x = v;
+    in.prow = pinv;
+    const int slot = c.tbegin(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
+    if (p == P_FP32) rc = gemv_partials(c, gm, n, P_FP32, Au, n, in, 0, pa, nullptr, nullptr, skip);
+    else rc = gemv_partials(c, gm, n, P_FP64, A, lda, in, 0, pa, nullptr, nullptr, skip);
+    c.tend(slot);
+    if (rc) return rc;
+  }
+  const int cls = inv_prec == P_FP32 ? MSIR_T_TRGEMV : MSIR_T_TRGEMV64;
+  {
+    GemvIn in;
+    in.xpart = pa; in.xns = gm.ns; in.xchunk = gm.chunk; in.xtri = 0; in.xround = p; in.xscale = Rp;
+    const int slot = c.tbegin(cls);
+    rc = gemv_partials(c, gl, n, inv_prec, X, n, in, 0, pb, nullptr, nullptr, skip);
+    c.tend(slot);
+    if (rc) return rc;
+  }
+  {
+    GemvIn in;
+    in.xpart = pb; in.xns = gl.ns; in.xchunk = gl.chunk; in.xtri = 1; in.xround = p;
+    const int slot = c.tbegin(cls);
+    rc = gemv_partials(c, gu, n, inv_prec, Y, n, in, 0, pa, nullptr, nullptr, skip);
+    if (!rc) rc = gemv_finish(c, gu, n, pa, nullptr, mu, S, u, out, nullptr, skip);
+    c.tend(slot);
+  }
+  return rc;
+}
+
 }  // namespace msir

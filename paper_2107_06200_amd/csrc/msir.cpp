@@ -155,6 +155,11 @@ int GmresOp::apply_solve(Ctx& c, const double* t, const int* skip, double* out, 
 }
 
 int GmresOp::apply_full(Ctx& c, const double* v, double* out, const int* skip) const {
+  if (Xinv && pinv) {
+    // fl_u(mu S Y fl_p(X P R fl_p(A v))) as three streaming products, each folding the
+    // previous one's partial sums while staging its input, and one final fold
+    return inv_operator(c, n, p, A, lda, Au, v, pinv, Rp, inv_prec, Xinv, Yinv, mu, S, u, out, skip);
+  }
   if (Xinv) {
     // A v is written already permuted and row-scaled (P R fl_p(A v)), the input of L^{-1}
     int rc = matvec(c, n, A, lda, Au, n, v, p, tmp_hi, tmp_lo, skip, perm, R);
@@ -204,9 +209,11 @@ struct FactorState {
   size_t Wbytes = 0;
   int* ipiv = nullptr;
   int* perm = nullptr;
+  int* pinv = nullptr;     // inverse permutation: pinv[perm[i]] = i
   double* rinv = nullptr;
   double* R = nullptr;
   double* S = nullptr;
+  double* Rp = nullptr;    // row scaling in pivot order: Rp[i] = R[perm[i]] (scaled factors)
   double* mu_dev = nullptr;
   double mu = 1.0;
   bool scaled = false;
@@ -222,7 +229,7 @@ struct msir_handle {
   bool inv64 = false, inv32 = false;  // inverses of the current factorization are valid
   double* dev_small = nullptr;   // device scalars
   double* host_small = nullptr;  // pinned host scalars
-  std::vector<int> hpiv, hperm;
+  std::vector<int> hpiv, hperm, hpinv;
   hipEvent_t ev[4];
 };
 
@@ -234,18 +241,20 @@ static int ensure_factor(msir_handle* h, int n, int prec) {
     if (h->c.alloc(&f.W, wb)) return MSIR_ERR_ALLOC;
     f.Wbytes = wb;
   }
-  const size_t vb = (size_t)n * (2 * sizeof(int) + 3 * sizeof(double)) + 64;
+  const size_t vb = (size_t)n * (3 * sizeof(int) + 4 * sizeof(double)) + 64;
   if (f.vec_bytes < vb) {
     if (f.rinv) { (void)hipStreamSynchronize(h->c.stream); h->c.release(f.rinv, f.vec_bytes); f.rinv = nullptr; }
     void* p = nullptr;
     if (h->c.alloc(&p, vb)) return MSIR_ERR_ALLOC;
     f.vec_bytes = vb;
-    char* q = (char*)p;                       // [rinv | R | S | ipiv | perm]
+    char* q = (char*)p;                       // [rinv | R | S | Rp | ipiv | perm | pinv]
     f.rinv = (double*)q; q += n * sizeof(double);
     f.R = (double*)q; q += n * sizeof(double);
     f.S = (double*)q; q += n * sizeof(double);
+    f.Rp = (double*)q; q += n * sizeof(double);
     f.ipiv = (int*)q; q += n * sizeof(int);
-    f.perm = (int*)q;
+    f.perm = (int*)q; q += n * sizeof(int);
+    f.pinv = (int*)q;
   }
   f.prec = prec;
   f.n = n;
@@ -316,7 +325,14 @@ static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, 
     const int k = h->hpiv[j];
     if (k != j) std::swap(h->hperm[j], h->hperm[k]);
   }
+  h->hpinv.resize(n);
+  for (int i = 0; i < n; ++i) h->hpinv[h->hperm[i]] = i;
   HIP_CHECK(hipMemcpyAsync(f.perm, h->hperm.data(), n * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  HIP_CHECK(hipMemcpyAsync(f.pinv, h->hpinv.data(), n * sizeof(int), hipMemcpyHostToDevice, c.stream));
+  if (f.scaled) {
+    rc = gather(c, n, f.R, f.perm, f.Rp);
+    if (rc) return rc;
+  }
   rc = diag_reciprocals(c, n, prec, f.W, n, f.rinv);
   if (rc) return rc;
   HIP_CHECK(hipStreamSynchronize(c.stream));
@@ -698,13 +714,26 @@ int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, co
   }
   if (!dperm || !rinv || !th || !tl) return MSIR_ERR_ALLOC;
   HIP_CHECK(hipMemcpyAsync(dperm, perm.data(), n * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
-  int rc = diag_reciprocals(h->c, n, f, dW, ldw, rinv);
+  // inverse permutation and R in pivot order, for the operator through the inverses
+  std::vector<int> pinv(n);
+  for (int i = 0; i < n; ++i) pinv[perm[i]] = i;
+  int* dpinv = (int*)vbuf(h, h->xb, n);
+  double* dRp = dR ? vbuf(h, h->d, n) : nullptr;
+  if (!dpinv || (dR && !dRp)) return MSIR_ERR_ALLOC;
+  HIP_CHECK(hipMemcpyAsync(dpinv, pinv.data(), n * sizeof(int), hipMemcpyHostToDevice, h->c.stream));
+  int rc = 0;
+  if (dR) {
+    rc = gather(h->c, n, dR, dperm, dRp);
+    if (rc) return rc;
+  }
+  rc = diag_reciprocals(h->c, n, f, dW, ldw, rinv);
   if (rc) return rc;
   double* t2 = vbuf(h, h->tmp2, n);
   if (!t2) return MSIR_ERR_ALLOC;
   GmresOp op;
   op.n = n; op.u = u; op.p = p; op.prec = f; op.mode = 0; op.A = dA; op.lda = lda; op.Au = Au; op.W = dW;
   op.ldw = ldw; op.perm = dperm; op.rinv = rinv; op.R = dR; op.S = dS; op.mu = dR ? mu : 1.0; op.dinv = nullptr;
+  op.pinv = dpinv; op.Rp = dRp;
   op.tmp_hi = th; op.tmp_lo = tl; op.tmp2 = t2;
   if (p != MSIR_DD) {
     // inverses of the caller's factors (the handle's cached inverses are invalidated)
@@ -915,6 +944,7 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
       op.W = h->f.W; op.ldw = n; op.perm = h->f.perm; op.rinv = h->f.rinv;
       op.R = h->f.scaled ? h->f.R : nullptr; op.S = h->f.scaled ? h->f.S : nullptr;
       op.mu = h->f.scaled ? h->f.mu : 1.0;
+      op.pinv = h->f.pinv; op.Rp = h->f.scaled ? h->f.Rp : nullptr;
       op.Xinv = op.Yinv = nullptr;
       op.inv_prec = -1;
       if (op.p != P_DD) {

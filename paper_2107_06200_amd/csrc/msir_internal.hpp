@@ -131,8 +131,26 @@ struct GemvPlan {
   int rb = 1;      // row blocks
   int ns = 1;      // column slices
   int chunk = 1;   // columns per slice
+  int nwg = 0;     // triangular: (row block, slice) pairs that meet the triangle
 };
 GemvPlan gemv_plan(int n, int tri);
+// Input of a streaming product: a plain vector x (optionally gathered, xin_j = R[perm[j]]
+// x[perm[j]]), or the partial sums of the producing product (xpart[s * n + j] over that
+// product's slices; its plan's ns, chunk and tri select the slices of element j), folded
+// in slice order, rounded to xround (-1: none) and multiplied by xscale[j] (may be null).
+// prow (may be null): the partial sum of row r is stored at column prow[r].
+struct GemvIn {
+  const double* x = nullptr;
+  const int* perm = nullptr;
+  const double* R = nullptr;
+  const double* xpart = nullptr;
+  int xns = 0, xchunk = 0, xtri = 0;
+  int xround = -1;
+  const double* xscale = nullptr;
+  const int* prow = nullptr;
+};
+int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const GemvIn& in, int mode,
+                  double* ph, double* pl, double* px, const int* skip);
 // a_prec FP32 (mode 0 only) or FP64; mode 0 float64 sums into ph, 1 double-double into
 // ph/pl, 2 both (double-double into ph/pl, float64 into px).  Buffers hold ns * n doubles.
 int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const double* x,
@@ -142,6 +160,13 @@ int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, i
 int gemv_finish(Ctx& c, const GemvPlan& g, int n, const double* ph, const double* pl, double mu, const double* S,
                 int p, double* y_hi, double* y_lo, const int* skip, const int* operm = nullptr,
                 const double* oR = nullptr);
+// out = fl_u(mu S Y fl_p(X P R fl_p(A v))): GMRES operator through the explicit inverses
+// X = L^{-1}, Y = U^{-1} (storage inv_prec); A v uses the fp32 copy Au when p == FP32.
+// pinv: inverse of the pivot permutation; Rp = R in pivot order (null: no row scaling).
+int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au, const double* v, const int* pinv,
+                 const double* Rp, int inv_prec, const void* X, const void* Y, double mu, const double* S, int u,
+                 double* out, const int* skip);
+int gather(Ctx& c, int n, const double* src, const int* idx, double* dst);
 int diag_block_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* dinv);
 size_t diag_inv_doubles(int n);
 

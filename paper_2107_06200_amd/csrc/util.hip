@@ -189,6 +189,19 @@ __global__ __launch_bounds__(UT) void k_round_vec(int n, const double* __restric
   if (i < n) out[i] = round_to(in[i], p);
 }
 
+__global__ __launch_bounds__(UT) void k_gather(int n, const double* __restrict__ src, const int* __restrict__ idx,
+                                              double* __restrict__ dst) {
+  const int i = blockIdx.x * UT + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+// dst[i] = src[idx[i]]
+int gather(Ctx& c, int n, const double* src, const int* idx, double* dst) {
+  k_gather<<<(n + UT - 1) / UT, UT, 0, c.stream>>>(n, src, idx, dst);
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
 int round_vec(Ctx& c, int n, const double* in, double* out, int p) {
   k_round_vec<<<(n + UT - 1) / UT, UT, 0, c.stream>>>(n, in, out, p);
   HIP_CHECK(hipGetLastError());
