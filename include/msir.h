@@ -75,7 +75,7 @@ typedef struct {
     msir_scale scaling;    /* Sec. 2.1.2 scaling policy                               */
     int    nb;             /* LU panel width; 0 = automatic (see msir_nb_auto)        */
     int    max_steps;      /* global cap on refinement steps (safety)                 */
-    int    lu_update;      /* trailing update of fp16/bf16 factors: MSIR_LU_MFMA
+    int    lu_update;      /* trailing update of fp16/bf16/fp32 factors: MSIR_LU_MFMA
                               (matrix cores, default) or MSIR_LU_FMA (sequential fp32
                               fused multiply-adds, k ascending: reproducible)       */
 } msir_params;
@@ -199,10 +199,10 @@ MSIR_API int msir_scaling(msir_handle* h, int n, const double* dA, int lda, msir
  * and dipiv[j] swapped at step j).  *info: 0, or k+1 for the first zero pivot
  * column k.  Factors: unit lower L below the diagonal, U on and above, all in f,
  * computed as described for the blocked model (panel in fp32 or fp64 registers,
- * rank-1 updates by fused multiply-add).  update (fp16/bf16 only): MSIR_LU_MFMA
+ * rank-1 updates by fused multiply-add).  update (fp16/bf16/fp32): MSIR_LU_MFMA
  * accumulates the trailing update on the matrix cores (fp32 accumulator, internal
  * summation order of the hardware); MSIR_LU_FMA with a sequential fp32 fused
- * multiply-add chain over k (bit-reproducible).  fp32/fp64 factors always use FMA. */
+ * multiply-add chain over k (bit-reproducible).  fp64 factors always use FMA.      */
 MSIR_API int msir_getrf(msir_handle* h, int n, msir_prec f, void* dW, int ldw, int nb, int update, int* dipiv,
                         int* info);
 

@@ -281,28 +281,38 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
 constexpr int SNT = 64;    // one column per thread, one wave per workgroup
 constexpr int MAXMOVE = 128;  // capacity of the moved-row list (at most 2 nb rows move per panel)
 
-// Every column outside the panel gets the panel's row permutation: all moved
-// values are loaded first (independent loads), then stored at their new rows.
-// Columns right of the panel then solve U12 = L11^{-1} A12 by forward
-// substitution (rows in increasing order, fused multiply-adds in the
-// arithmetic format) and store it rounded to u_f.
+// Every column outside the panel gets the panel's row permutation, and columns right
+// of the panel then solve U12 = L11^{-1} A12 by forward substitution (rows in
+// increasing order, fused multiply-adds in the arithmetic format), stored rounded to
+// u_f.  Round trips: (1) the moved-row list with its count and L11; (2) every moved
+// value and, for panels up to 32 wide, the interchanged A12 read straight from its
+// source rows (recorded per pivot row in step (1)), all in flight together; wider
+// panels read A12 after the interchange stores (register budget).
 template <int P, int KMAX, int MM = 2 * KMAX>
 __global__ __launch_bounds__(SNT) void k_swap_trsm(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0,
                                                    int jb, const int* __restrict__ moved) {
   typedef typename Arith<P>::T AT;
   typedef typename Store<P>::T ST;
+  constexpr bool EARLY = KMAX <= 32;
   const int tid = threadIdx.x;
   const int jr = j0 + jb;
-  __shared__ int sdst[MM], ssrc[MM];
+  __shared__ int sdst[MM], ssrc[MM], sa12[KMAX];
   __shared__ AT sL[KMAX][KMAX + 1];
   __shared__ int s_cnt;
+  // (1) list (count in moved[0], then (dst, src) pairs) and L11
   if (tid == 0) s_cnt = moved[0];
+  for (int i = tid; i < MM; i += SNT) { sdst[i] = moved[1 + 2 * i]; ssrc[i] = moved[2 + 2 * i]; }
+  for (int e = tid; e < KMAX * KMAX; e += SNT) {
+    const int i = e % KMAX, k = e / KMAX;
+    sL[i][k] = (i < jb && k < jb) ? to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + i], AT(0)) : AT(0);
+  }
+  for (int k = tid; k < KMAX; k += SNT) sa12[k] = j0 + k;
   __syncthreads();
-  const int cnt = s_cnt;
-  for (int i = tid; i < cnt; i += SNT) { sdst[i] = moved[1 + 2 * i]; ssrc[i] = moved[2 + 2 * i]; }
-  for (int e = tid; e < jb * jb; e += SNT) {
-    const int i = e % jb, k = e / jb;
-    sL[i][k] = to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + i], AT(0));
+  const int cnt = min(s_cnt, MM);
+  // source row of the value that lands on pivot row j0 + k
+  for (int i = tid; i < cnt; i += SNT) {
+    const int k = sdst[i] - j0;
+    if (k >= 0 && k < jb) sa12[k] = ssrc[i];
   }
   __syncthreads();
   // column index: skip the panel columns
@@ -310,18 +320,26 @@ __global__ __launch_bounds__(SNT) void k_swap_trsm(typename Store<P>::T* __restr
   if (col >= j0) col += jb;
   if (col >= n) return;
   ST* w = W + (size_t)col * ldw;
+  const bool right = col >= jr;
+  // (2) moved values (and A12 from its source rows)
   ST v[MM];
+  AT u[KMAX];
 #pragma unroll
   for (int i = 0; i < MM; ++i)
     if (i < cnt) v[i] = w[ssrc[i]];
+  if (EARLY) {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) u[k] = (right && k < jb) ? to_a<P>(w[sa12[k]], AT(0)) : AT(0);
+  }
 #pragma unroll
   for (int i = 0; i < MM; ++i)
     if (i < cnt) w[sdst[i]] = v[i];
-  if (col < jr) return;
-  // same-thread loads after the stores above see the interchanged values
-  AT u[KMAX];
+  if (!right) return;
+  if (!EARLY) {
+    // same-thread loads after the stores above see the interchanged values
 #pragma unroll
-  for (int k = 0; k < KMAX; ++k) u[k] = (k < jb) ? to_a<P>(w[j0 + k], AT(0)) : AT(0);
+    for (int k = 0; k < KMAX; ++k) u[k] = (k < jb) ? to_a<P>(w[j0 + k], AT(0)) : AT(0);
+  }
 #pragma unroll
   for (int k = 1; k < KMAX; ++k) {
     if (k < jb) {
@@ -339,7 +357,8 @@ __global__ __launch_bounds__(SNT) void k_swap_trsm(typename Store<P>::T* __restr
 
 // ------------------------------------------------------------------ trailing update
 // A22 <- fl_f(A22 - L21 U12), 64x64 output tile per workgroup (4 waves, 2x2
-// 32x32 MFMA tiles for fp16/bf16; 4x4 register micro-tiles for fp32/fp64).
+// 32x32 MFMA tiles for fp16/bf16 and fp32 factors; 4x4 register micro-tiles with
+// sequential FMA chains for fp64 factors and for the reproducible FMA mode).
 // L21 (64 x jb) and U12 (jb x 64) are staged through LDS with coalesced loads.
 constexpr int GT = 64;
 constexpr int GNT = 256;
@@ -373,17 +392,18 @@ __global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__
   const int c0 = jr + blockIdx.y * GT;
   __shared__ ST sA[GT][KMAX + 4];   // L21 tile, [row][k]
   __shared__ ST sB[GT][KMAX + 4];   // U12 tile, [col][k]
-  // stage L21: column k of the tile is 64 contiguous rows
-  for (int e = tid; e < GT * jb; e += GNT) {
+  // stage L21: column k of the tile is 64 contiguous rows (k >= jb zero-filled: the
+  // matrix-core paths consume k in steps of 8 or 2)
+  for (int e = tid; e < GT * KMAX; e += GNT) {
     const int i = e % GT, k = e / GT;
     const int r = r0 + i;
-    sA[i][k] = (r < n) ? W[(size_t)(j0 + k) * ldw + r] : (ST)0;
+    sA[i][k] = (r < n && k < jb) ? W[(size_t)(j0 + k) * ldw + r] : (ST)0;
   }
   // stage U12: column c of the tile holds jb contiguous values
-  for (int e = tid; e < GT * jb; e += GNT) {
-    const int k = e % jb, q = e / jb;
+  for (int e = tid; e < GT * KMAX; e += GNT) {
+    const int k = e % KMAX, q = e / KMAX;
     const int c = c0 + q;
-    sB[q][k] = (c < n) ? W[(size_t)c * ldw + j0 + k] : (ST)0;
+    sB[q][k] = (c < n && k < jb) ? W[(size_t)c * ldw + j0 + k] : (ST)0;
   }
   __syncthreads();
   if constexpr ((P == P_FP16 || P == P_BF16) && MF) {
@@ -440,6 +460,55 @@ __global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__
         for (int e = 0; e < 4; ++e) {
           const int r = r0 + tr + 8 * g + 4 * hi + e;
           if (r < n) W[(size_t)col * ldw + r] = Store<P>::from_f(acc[4 * g + e]);
+        }
+    }
+  } else if constexpr (P == P_FP32 && MF) {
+    // fp32 factors on the matrix cores: v_mfma_f32_32x32x2f32, K = 2 per instruction;
+    // the accumulator layout is that of the 32x32x8 f16 instruction above
+    const int lane = tid & 63, wv = tid >> 6;
+    const int lc = lane & 31, hi = lane >> 5;
+    const int tr = (wv & 1) * 32, tc = (wv >> 1) * 32;
+    const int col = c0 + tc + lc;
+    const bool vec = ((ldw & 3) == 0) && ((r0 & 3) == 0) && (r0 + tr + 32 <= n) && (col < n) &&
+                     (((uintptr_t)W & 15) == 0);
+    float16_t acc;
+    if (vec) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const float4 q = *reinterpret_cast<const float4*>(W + (size_t)col * ldw + r0 + tr + 8 * g + 4 * hi);
+        acc[4 * g + 0] = q.x; acc[4 * g + 1] = q.y; acc[4 * g + 2] = q.z; acc[4 * g + 3] = q.w;
+      }
+    } else {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tr + 8 * g + 4 * hi + e;
+          acc[4 * g + e] = (col < n && r < n) ? W[(size_t)col * ldw + r] : 0.0f;
+        }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KMAX; kk += 2) {
+      if (kk < jb) {
+        const float av = -sA[tr + lc][kk + hi];
+        const float bv = sB[tc + lc][kk + hi];
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(av, bv, acc, 0, 0, 0);
+      }
+    }
+    if (vec) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        float4 q;
+        q.x = acc[4 * g + 0]; q.y = acc[4 * g + 1]; q.z = acc[4 * g + 2]; q.w = acc[4 * g + 3];
+        *reinterpret_cast<float4*>(W + (size_t)col * ldw + r0 + tr + 8 * g + 4 * hi) = q;
+      }
+    } else if (col < n) {
+#pragma unroll
+      for (int g = 0; g < 4; ++g)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int r = r0 + tr + 8 * g + 4 * hi + e;
+          if (r < n) W[(size_t)col * ldw + r] = acc[4 * g + e];
         }
     }
   } else {
@@ -552,7 +621,7 @@ static int getrf_p(Ctx& c, int n, void* W, int ldw, int nb, int* ipiv, int* info
 }
 
 int getrf(Ctx& c, int n, int prec, void* W, int ldw, int nb, int* ipiv, int* info_dev, int update) {
-  const bool mf = update == MSIR_LU_MFMA && (prec == P_FP16 || prec == P_BF16);
+  const bool mf = update == MSIR_LU_MFMA && prec != P_FP64;
   if (nb == 0) nb = nb_auto(n, prec);
   if (!nb_ok(n, prec, nb)) return -6;
   HIP_CHECK(hipMemsetAsync(info_dev, 0, sizeof(int), c.stream));
