@@ -39,7 +39,21 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lu-update", choices=["mfma", "fma"], default="mfma",
                     help="trailing update of the fp16/bf16 LU: matrix cores or fp32 FMA chains")
+    ap.add_argument("--copy-only", type=int, default=0, metavar="MB",
+                    help="only copy MB megabytes device to device once (calibrates HBM byte counters)")
     return ap.parse_args()
+
+
+def copy_only(mb):
+    """One device-to-device copy of a known size: the reference for FETCH_SIZE/WRITE_SIZE."""
+    import torch
+    n = mb * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda:0")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 4 * n, "read_bytes": 4 * n, "written_bytes": 4 * n}))
 
 
 # Bytes one launch of each memory-bound class must move at minimum: the matrix operand
@@ -54,6 +68,32 @@ def algorithmic_bytes(cls, n):
             "trgemv64": 8 * tri + 16 * n,         # one fp64 inverse triangle
             "resid": 8 * n * n + 40 * n,          # A, x, b in; r, r_hat out
             }.get(cls)
+
+
+# Kernel sources the GEMV classes are built from; HBM traffic figures taken with the
+# byte counters are used only while these are unchanged.
+GEMV_SOURCES = ["paper_2107_06200_amd/csrc/gemv.hip", "paper_2107_06200_amd/csrc/inverse.hip",
+                "paper_2107_06200_amd/csrc/common.hpp", "paper_2107_06200_amd/csrc/msir_internal.hpp"]
+TRAFFIC_FILE = "profiles/msir_n4096_gemv_hbm_counters.md"
+
+
+def measured_traffic(cls, n):
+    """HBM bytes per launch of class `cls` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE runs calibrated on a copy of known size), or None when there is no figure for
+    this class and order or the kernel sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        txt = open(os.path.join(ROOT, TRAFFIC_FILE)).read()
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in GEMV_SOURCES)).hexdigest()[:16]
+    except OSError:
+        return None
+    if n != 4096:
+        return None
+    m = re.search(r"traffic_bytes_per_launch\[%s\] = (\d+) \(kernel sources sha256 ([0-9a-f]+)\)" % re.escape(cls), txt)
+    if not m or m.group(2) != h:
+        return None
+    return int(m.group(1))
 
 
 def cpu_baseline(A, b, hs):
@@ -114,6 +154,9 @@ def cpu_baseline(A, b, hs):
 
 def main():
     args = parse()
+    if args.copy_only:
+        copy_only(args.copy_only)
+        return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the solver is a single-device library; "
               "--gpus %d is not supported (see the design notes for how it would shard)" % args.gpus,
@@ -177,7 +220,7 @@ def main():
     byt = algorithmic_bytes(dom, n)
     ach = byt / (avg_ms * 1e-3) / 1e9
     roof = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "bytes_per_launch": byt,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dom, n), "bytes_per_launch": byt,
             "avg_launch_ms": round(avg_ms, 5), "launches": launches, "largest_class": dom_all}
 
     # FP64 getrf + getrs on the same GPU (black-box comparator)
