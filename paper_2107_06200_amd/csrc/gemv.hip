@@ -5,20 +5,20 @@
 // A v inside GMRES (float32 copy of A or float64 A, Alg. 2/3), and the two
 // triangular products that apply M^{-1} through the explicit inverses.
 //
-// Layout of one launch: a workgroup of 16 waves owns 256 consecutive rows and
-// one slice of columns.  Lane l of wave w holds rows 4l..4l+3 and the columns
-// w, w+16, w+32, ... of the slice, so one load instruction of a wave reads 256
-// contiguous rows of one column (1 KiB fp32, 2 KiB fp64) with 16-byte vector
-// loads, and each lane keeps eight columns in flight.  The 16 waves' sums are
-// folded in LDS in wave order and each workgroup writes one partial per row;
-// a second kernel adds the slices' partials in slice order.  Results are
-// therefore reproducible run to run, and there are no atomics or device-wide
-// fences on the streaming path.
+// Layout of one launch: a workgroup of WV waves (8 or 16) owns 256 consecutive
+// rows and one slice of columns.  Wave w takes the columns w, w+WV, w+2WV, ... of
+// the slice; each lane holds four of the 256 rows (lane_row), so that one load
+// instruction of a wave reads 1 KiB of one column contiguously with 16-byte loads,
+// and each lane keeps four or eight columns in flight.  The waves' sums are folded
+// in LDS in wave order and each workgroup writes one partial per row; the slices'
+// partials are added in slice order by a finishing kernel, or by the staging step
+// of the next product.  Results are therefore reproducible run to run, and there
+// are no atomics or device-wide fences on the streaming path.
 //
-// Triangular operands: only workgroups whose (row block, slice) meets the
-// triangle are given work (the slice width is chosen so that about one
-// workgroup per compute unit is busy); inside the diagonal blocks, lanes whose
-// rows lie outside the triangle for a column skip its load.
+// Triangular operands: a compact grid holds only the (row block, slice) pairs that
+// meet the triangle (the slice width is chosen so that about one workgroup per
+// compute unit is busy); inside the diagonal blocks, entries outside the triangle
+// are multiplied as exact zeros.
 //
 // Accumulation is float64 (fused multiply-add).  MODE 1 accumulates in
 // double-double with exact products (u_r = quadruple-precision stand-in);
@@ -34,33 +34,49 @@ constexpr int GV_MAXCHUNK = 2048;            // columns per slice (LDS staging b
 constexpr int GV_TARGET = 256;               // busy workgroups per launch
 constexpr int GV_BATCH = 128;                // slice widths are multiples of this
 
-// Four consecutive rows of one column in the matrix's own type (one 16-byte load for
-// fp32, two for fp64, when aligned and all four rows exist).
+// Lane row layout inside a 256-row block.  fp32: lane l holds rows 4l..4l+3 (one
+// 16-byte load per column: a wave instruction reads 1 KiB contiguous).  fp64: lane l
+// holds rows 2l, 2l+1 and 128+2l, 129+2l (two 16-byte loads per column, each wave
+// instruction again 1 KiB contiguous, so no cache line is requested twice).
 template <typename TA>
-__device__ __forceinline__ void load4(const TA* __restrict__ p, bool vec, int valid, TA v[4]) {
+__device__ __forceinline__ int lane_row(int lane, int e) {
+  if constexpr (sizeof(TA) == 8) return (e >> 1) * 128 + 2 * lane + (e & 1);
+  else return 4 * lane + e;
+}
+
+// One column's four entries for this lane, in the matrix's own type.  `pc` is the
+// column, rA / rB the first rows of the lane's row groups (rB only for fp64) and
+// vA / vB how many rows of each group exist; missing rows read as zero.
+template <typename TA>
+__device__ __forceinline__ void load_col4(const TA* __restrict__ pc, int rA, int rB, int vA, int vB, bool vec,
+                                          TA v[4]) {
   if constexpr (sizeof(TA) == 4) {
     if (vec) {
-      const float4 q = *reinterpret_cast<const float4*>(p);
+      const float4 q = *reinterpret_cast<const float4*>(pc + rA);
       v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
       return;
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (e < vA) ? pc[rA + e] : TA(0);
   } else {
     if (vec) {
-      const double2 q0 = *reinterpret_cast<const double2*>(p);
-      const double2 q1 = *reinterpret_cast<const double2*>(p + 2);
+      const double2 q0 = *reinterpret_cast<const double2*>(pc + rA);
+      const double2 q1 = *reinterpret_cast<const double2*>(pc + rB);
       v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
       return;
     }
+    v[0] = (vA > 0) ? pc[rA] : 0.0;
+    v[1] = (vA > 1) ? pc[rA + 1] : 0.0;
+    v[2] = (vB > 0) ? pc[rB] : 0.0;
+    v[3] = (vB > 1) ? pc[rB + 1] : 0.0;
   }
-#pragma unroll
-  for (int e = 0; e < 4; ++e) v[e] = (e < valid) ? p[e] : TA(0);
 }
 
-// Does lane row block [r0, r0+4) need column j of a TRI-triangular operand?
+// Does a row group [rmin, rmax] need column j of a TRI-triangular operand?
 template <int TRI>
-__device__ __forceinline__ bool needs(int j, int r0) {
-  if (TRI == 1) return j <= r0 + 3;   // lower: T_ij != 0 only for j <= i
-  if (TRI == 2) return j >= r0;       // upper: j >= i
+__device__ __forceinline__ bool needs(int j, int rmin, int rmax) {
+  if (TRI == 1) return j <= rmax;   // lower: T_ij != 0 only for j <= i
+  if (TRI == 2) return j >= rmin;   // upper: j >= i
   return true;
 }
 
@@ -91,13 +107,9 @@ __device__ __forceinline__ void slice_range(int n, int rb, int s, int chunk, int
 
 // part_hi[s * n + row] (and part_lo, part_x by MODE) = sum over slice s of T[row, j] xin[j],
 // xin[j] = perm ? R[perm[j]] x[perm[j]] (R may be null) : x[j].
-// WV waves per workgroup (column groups).  Full products: 16 for fp32 and the
-// double-double modes, 8 for plain float64 (eight 32-byte columns in flight per lane
-// need the register budget of a 512-thread workgroup).  Triangular products: 8, with
-// four float64 columns in flight, so that two workgroups fit on a compute unit and
-// every busy (row block, slice) pair of the compact grid is resident at once; a
-// second dispatch round would double the time of these short launches.
-template <typename TA, int MODE, int TRI, int WV>
+// WV waves per workgroup (column groups) and DB (double-buffered batches) per
+// configuration, as gemv_waves / gemv_dbuf choose them.
+template <typename TA, int MODE, int TRI, int WV, bool DB>
 __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ A, int lda, bool aligned, GemvIn in,
                                                int chunk, double* __restrict__ p_hi, double* __restrict__ p_lo,
                                                double* __restrict__ p_x, const int* __restrict__ skip) {
@@ -165,18 +177,25 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   }
   // 2. the first batch of matrix columns, in flight before the slice is needed
   const int rlo = rb * GV_ROWS;
-  const int r0 = rlo + 4 * lane;
-  const int valid = max(0, min(4, n - r0));
-  const bool vec = aligned && valid == 4;
-  const TA* a = A + min(r0, n - 1);
+  constexpr bool SPLIT = sizeof(TA) == 8;
+  const int rA = rlo + lane_row<TA>(lane, 0);
+  const int rB = rA + 128;
+  const int vA = max(0, min(SPLIT ? 2 : 4, n - rA));
+  const int vB = SPLIT ? max(0, min(2, n - rB)) : 0;
+  const bool vec = aligned && (SPLIT ? (vA == 2 && vB == 2) : vA == 4);
+  // row groups for the triangle test: fp32 one group of four rows, fp64 two pairs
+  const int gmin0 = rA, gmax0 = rA + (SPLIT ? 1 : 3);
+  const int gmin1 = rB, gmax1 = rB + 1;
   constexpr int UNR = (sizeof(TA) == 4 || (MODE == 0 && TRI == 0)) ? 8 : 4;   // columns in flight per lane
   static_assert(UNR * GV_WAVES <= GV_BATCH && GV_BATCH % (UNR * GV_WAVES) == 0, "slices must be whole batches");
-  TA v[UNR][4];
+  constexpr int STEP = UNR * GV_WAVES;   // columns a workgroup consumes per batch
+  TA va[UNR][4];
   int j = j0 + w;
-  if (valid > 0) {
+  auto load_batch = [&](TA (&vv)[UNR][4], int jj) {
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) load4<TA>(a + (size_t)min(j + u * GV_WAVES, j1 - 1) * lda, vec, valid, v[u]);
-  }
+    for (int u = 0; u < UNR; ++u) load_col4<TA>(A + (size_t)min(jj + u * GV_WAVES, j1 - 1) * lda, rA, rB, vA, vB, vec, vv[u]);
+  };
+  if (vA > 0) load_batch(va, j);
   // 3. slice into LDS
   if (!in.xpart) {
 #pragma unroll
@@ -194,35 +213,65 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
     }
   }
   __syncthreads();
-  // 4. batches of UNR columns per wave: accumulate the batch (columns past the slice or
-  // outside the triangle contribute exact zeros), then load the next one
+  // 4. batches of UNR columns per wave.  Loads are unconditional (column index clamped;
+  // past-the-slice and outside-the-triangle columns contribute exact zeros).
   double h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0}, f[4] = {0, 0, 0, 0};
-  if (valid > 0) {
-    for (;;) {
+  auto use_batch = [&](const TA (&vv)[UNR][4], int jj) {
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int col = j + u * GV_WAVES;
-        const bool ok = col < j1 && needs<TRI>(col, r0);
-        const double xv = ok ? sx[min(col, j1 - 1) - j0] : 0.0;
-        double vv[4];
+    for (int u = 0; u < UNR; ++u) {
+      const int col = jj + u * GV_WAVES;
+      const bool in_slice = col < j1;
+      const bool ok0 = in_slice && needs<TRI>(col, gmin0, gmax0);
+      const bool ok1 = SPLIT ? (in_slice && needs<TRI>(col, gmin1, gmax1)) : ok0;
+      const double xv = in_slice ? sx[min(col, j1 - 1) - j0] : 0.0;
+      double v4[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) vv[e] = ok ? (double)v[u][e] : 0.0;
-        accum<MODE>(vv, xv, h, l, f);
+      for (int e = 0; e < 4; ++e) v4[e] = ((SPLIT && e >= 2) ? ok1 : ok0) ? (double)vv[u][e] : 0.0;
+      accum<MODE>(v4, xv, h, l, f);
+    }
+  };
+  if (vA > 0) {
+    if constexpr (DB) {
+      // double-buffered: the next batch's loads are issued before the current one is
+      // consumed; the first NBU batches are straight-line code so that every wait on a
+      // batch leaves the following batch in flight
+      constexpr int NBU = 16;
+      TA vb[UNR][4];
+      bool more = true;
+#pragma unroll
+      for (int bt = 0; bt < NBU; bt += 2) {
+        load_batch(vb, j + STEP);
+        use_batch(va, j);
+        j += STEP;
+        if (j >= j1) { more = false; break; }
+        load_batch(va, j + STEP);
+        use_batch(vb, j);
+        j += STEP;
+        if (j >= j1) { more = false; break; }
       }
-      j += UNR * GV_WAVES;
-      if (j >= j1) break;
-#pragma unroll
-      for (int u = 0; u < UNR; ++u) load4<TA>(a + (size_t)min(j + u * GV_WAVES, j1 - 1) * lda, vec, valid, v[u]);
+      while (more) {   // slices wider than NBU batches: the rest single-buffered (va is loaded)
+        use_batch(va, j);
+        j += STEP;
+        if (j >= j1) break;
+        load_batch(va, j);
+      }
+    } else {
+      for (;;) {
+        use_batch(va, j);
+        j += STEP;
+        if (j >= j1) break;
+        load_batch(va, j);
+      }
     }
   }
-  // fold the 16 waves' sums in wave order (LDS reused: wait until every wave is done with sx)
+  // fold the waves' sums in wave order (LDS reused: wait until every wave is done with sx)
   __syncthreads();
   double* sh = lds;
   double* sl = lds + GV_WAVES * GV_ROWS;
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    sh[w * GV_ROWS + 4 * lane + e] = h[e];
-    if (MODE != 0) sl[w * GV_ROWS + 4 * lane + e] = l[e];
+    sh[w * GV_ROWS + lane_row<TA>(lane, e)] = h[e];
+    if (MODE != 0) sl[w * GV_ROWS + lane_row<TA>(lane, e)] = l[e];
   }
   __syncthreads();
   if (tid < GV_ROWS && rlo + tid < n) {
@@ -238,7 +287,7 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   if (MODE == 2) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 4; ++e) sh[w * GV_ROWS + 4 * lane + e] = f[e];
+    for (int e = 0; e < 4; ++e) sh[w * GV_ROWS + lane_row<TA>(lane, e)] = f[e];
     __syncthreads();
     if (tid < GV_ROWS && rlo + tid < n) {
       double tx = sh[tid];
@@ -313,19 +362,33 @@ GemvPlan gemv_plan(int n, int tri) {
   return g;
 }
 
+// Waves per workgroup, and double buffering, per configuration (measured on n = 4096):
+// float32 full products use 16 waves of eight columns in flight; float32 triangles 8
+// waves, double-buffered (the compact grid keeps every busy pair resident); float64
+// float64-accumulated products 8 waves (two batches of float64 columns need the
+// register budget of a 512-thread workgroup); double-double modes 16 waves.
+static constexpr int gemv_waves(bool fp32, int mode, int tri) {
+  return mode != 0 ? 16 : (fp32 && tri == 0 ? 16 : 8);
+}
+static constexpr bool gemv_dbuf(bool fp32, int mode, int tri) { return fp32 && mode == 0 && tri != 0; }
+
+template <typename TA, int MODE, int TRI>
+static void launch_one(Ctx& c, int grid_x, int grid_y, int n, const TA* A, int lda, bool aligned, const GemvIn& in,
+                       int chunk, double* ph, double* pl, double* px, const int* skip) {
+  constexpr bool F32 = sizeof(TA) == 4;
+  constexpr int WV = gemv_waves(F32, MODE, TRI);
+  constexpr bool DB = gemv_dbuf(F32, MODE, TRI);
+  k_gemv<TA, MODE, TRI, WV, DB><<<dim3(grid_x, grid_y), 64 * WV, 0, c.stream>>>(n, A, lda, aligned, in, chunk, ph, pl,
+                                                                              px, skip);
+}
+
 template <typename TA, int MODE>
 static void launch_gemv(Ctx& c, const GemvPlan& g, int n, const TA* A, int lda, const GemvIn& in, double* ph,
                         double* pl, double* px, const int* skip) {
-  constexpr int WV = (sizeof(TA) == 8 && MODE == 0) ? 8 : 16;
-  constexpr int WVT = (MODE == 0) ? 8 : 16;
   const bool aligned = ((uintptr_t)A % 16 == 0) && (lda % 4 == 0);
-  if (g.tri == 0)
-    k_gemv<TA, MODE, 0, WV><<<dim3(g.rb, g.ns), 64 * WV, 0, c.stream>>>(n, A, lda, aligned, in, g.chunk, ph, pl, px,
-                                                                        skip);
-  else if (g.tri == 1)
-    k_gemv<TA, MODE, 1, WVT><<<g.nwg, 64 * WVT, 0, c.stream>>>(n, A, lda, aligned, in, g.chunk, ph, pl, px, skip);
-  else
-    k_gemv<TA, MODE, 2, WVT><<<g.nwg, 64 * WVT, 0, c.stream>>>(n, A, lda, aligned, in, g.chunk, ph, pl, px, skip);
+  if (g.tri == 0) launch_one<TA, MODE, 0>(c, g.rb, g.ns, n, A, lda, aligned, in, g.chunk, ph, pl, px, skip);
+  else if (g.tri == 1) launch_one<TA, MODE, 1>(c, g.nwg, 1, n, A, lda, aligned, in, g.chunk, ph, pl, px, skip);
+  else launch_one<TA, MODE, 2>(c, g.nwg, 1, n, A, lda, aligned, in, g.chunk, ph, pl, px, skip);
 }
 
 int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const GemvIn& in, int mode,
@@ -333,9 +396,7 @@ int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, i
   if (n <= 0) return 0;
   if (in.xpart) {
     // fold-mode staging needs a thread per slice element: workgroup size as launched
-    int nt;
-    if (g.tri == 0) nt = (a_prec == P_FP64 && mode == 0) ? 512 : 1024;
-    else nt = (mode == 0) ? 512 : 1024;
+    const int nt = 64 * gemv_waves(a_prec == P_FP32, mode, g.tri);
     if (g.chunk > nt || in.xchunk < 1 || in.xns < 1) return -3;
   }
   if (a_prec == P_FP32) {
