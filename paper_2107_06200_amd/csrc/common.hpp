@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 #include <math.h>
+#include <type_traits>
 
 #define MSIR_WAVE 64
 
@@ -211,9 +212,12 @@ __device__ __forceinline__ int wave_or(int v) {
 // result is the same on every run.
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ double dpp_d(double v) {
+  // No "old" operand: lanes of rows outside ROWMASK receive unspecified values.  The
+  // full-mask steps below write every lane; the two row-broadcast steps leave rows 0
+  // and 2 unspecified, which no caller reads (the total is taken from lane 63).
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)b, CTRL, ROWMASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xF, false);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 __device__ __forceinline__ double wave_sum_dpp(double v) {

@@ -69,8 +69,8 @@ template <> struct PivKey<float> {
   __device__ float val() const { return __uint_as_float((uint32_t)(k >> 32)); }
   template <int CTRL, int RM> __device__ PivKey dpp() const {
     PivKey r;
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)k, CTRL, RM, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(k >> 32), CTRL, RM, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)k, CTRL, RM, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(k >> 32), CTRL, RM, 0xF, false);
     r.k = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
     return r;
   }
@@ -99,10 +99,10 @@ template <> struct PivKey<double> {
   __device__ double val() const { return __builtin_bit_cast(double, v); }
   template <int CTRL, int RM> __device__ PivKey dpp() const {
     PivKey r;
-    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)v, CTRL, RM, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(v >> 32), CTRL, RM, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, RM, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, RM, 0xF, false);
     r.v = ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
-    r.p = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)p, CTRL, RM, 0xF, false);
+    r.p = (uint32_t)__builtin_amdgcn_mov_dpp((int)p, CTRL, RM, 0xF, false);
     return r;
   }
   __device__ PivKey lane(int l) const {
@@ -131,7 +131,9 @@ __device__ __forceinline__ K kmax_step(K x) {
   return y.gt(x) ? y : x;
 }
 
-// Largest key of the wave (the DPP pattern of wave_sum_dpp with max), uniform.
+// Largest key of the wave (the DPP pattern of wave_sum_dpp with max), uniform.  The
+// moves carry no "old" operand: the row-broadcast steps leave rows 0 and 2 with
+// unspecified keys, and only lane 63 is read.
 template <typename K>
 __device__ __forceinline__ K wave_max_key(K x) {
   x = kmax_step<K, 0xB1, 0xF>(x);

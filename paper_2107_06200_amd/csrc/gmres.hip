@@ -28,13 +28,17 @@ constexpr int GNT = 1024;
 
 // beta = ||resid||_2; g[0] = beta; V0 = fl_u(resid / beta); status reset
 __global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __restrict__ resid, double* __restrict__ V0,
-                                                     double* __restrict__ g, double* __restrict__ beta0, int first,
-                                                     int u, GStatus* st) {
+                                                     float* __restrict__ V0f, double* __restrict__ g,
+                                                     double* __restrict__ beta0, int first, int u, GStatus* st) {
   __shared__ double sh[GNT / 64];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += GNT) acc = __fma_rn(resid[i], resid[i], acc);
   const double beta = sqrt(block_sum<GNT>(acc, sh));
-  for (int i = threadIdx.x; i < n; i += GNT) V0[i] = round_to(resid[i] / beta, u);
+  for (int i = threadIdx.x; i < n; i += GNT) {
+    const double v = round_to(resid[i] / beta, u);
+    V0[i] = v;
+    if (V0f) V0f[i] = (float)v;   // exact: v is representable in u (u != fp64)
+  }
   if (threadIdx.x == 0) {
     g[0] = beta;
     if (first) *beta0 = beta;
@@ -49,23 +53,23 @@ __global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __rest
 // barrier), w <- fl_u(w - h B).  h goes to the LDS copy of the Hessenberg column
 // (sHc, when the column fits) or straight to H (stored by every lane, same value,
 // so that all waves issue the same memory operations).
-template <int G, int U, int NT>
-__device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], const double (&B)[G],
+template <int G, int U, int NT, bool TAIL, typename VT>
+__device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], const VT (&B)[G],
                                          double* __restrict__ H, int ldh, double (*sh)[NT / 64], bool lds_col,
                                          double* sHc) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   double acc = 0.0;
 #pragma unroll
-  for (int t = 0; t < G; ++t) acc = __fma_rn(B[t], w[t], acc);
+  for (int t = 0; t < G; ++t) acc = __fma_rn((double)B[t], w[t], acc);
   acc = wave_sum_dpp(acc);
   if (lane == 0) sh[i & 1][wv] = acc;
   __syncthreads();
   const double h = sum_lanes<NT / 64>(sh[i & 1]);
 #pragma unroll
   for (int t = 0; t < G; ++t) {
-    const double nw = round_c<U>(__dsub_rn(w[t], __dmul_rn(h, B[t])));
-    w[t] = (tid + t * NT < n) ? nw : 0.0;
+    const double nw = round_c<U>(__dsub_rn(w[t], __dmul_rn(h, (double)B[t])));
+    w[t] = (!TAIL || tid + t * NT < n) ? nw : 0.0;   // rows past n stay zero
   }
   if (lds_col) {
     if (tid == 0) sHc[i] = h;
@@ -75,10 +79,9 @@ __device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], co
 }
 
 // Load column c of V into B (row indices clamped to the matrix).
-template <int G>
-__device__ __forceinline__ void load_col(double (&B)[G], const double* __restrict__ V, int ldv, int c,
-                                         const int (&rc)[G]) {
-  const double* vp = V + (size_t)c * ldv;
+template <int G, typename VT>
+__device__ __forceinline__ void load_col(VT (&B)[G], const VT* __restrict__ V, int ldv, int c, const int (&rc)[G]) {
+  const VT* vp = V + (size_t)c * ldv;
 #pragma unroll
   for (int t = 0; t < G; ++t) B[t] = vp[rc[t]];
 }
@@ -91,11 +94,12 @@ __device__ __forceinline__ void load_col(double (&B)[G], const double* __restric
 // straight-line code with a ring of D basis vectors in flight (the refill of a slot
 // is issued right after the slot is consumed), so the loads of v_{i+D} overlap D
 // inner products; beyond JU a rolled loop loads each vector when it is needed.
+// TAIL: n < G * NT, so that some lanes hold rows past n (kept at zero).
 constexpr int JU = 64;
 constexpr int JL = 512;   // Hessenberg columns up to this length are rotated in LDS
-template <int G, int U, int D, int NT>
-__global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict__ V, int ldv,
-                                                 const double* __restrict__ w_in, double* __restrict__ H, int ldh,
+template <int G, int U, int D, int NT, bool TAIL>
+__global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict__ V, float* __restrict__ Vf,
+                                                 int ldv, const double* __restrict__ w_in, double* __restrict__ H, int ldh,
                                                  double* __restrict__ cs, double* __restrict__ sn,
                                                  double* __restrict__ g, const double* __restrict__ beta0, double tau,
                                                  GStatus* st) {
@@ -125,19 +129,24 @@ __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict
     const double v = w_in[rc[t]];
     w[t] = r < n ? v : 0.0;
   }
-  double B[D][G];
+  // the inner products read the basis in the working format (float32 copy unless u is
+  // float64; the values are the same), which halves their memory traffic
+  typedef typename std::conditional<U == P_FP64, double, float>::type VT;
+  const VT* Vr;
+  if constexpr (U == P_FP64) Vr = V; else Vr = Vf;
+  VT B[D][G];
 #pragma unroll
-  for (int d = 0; d < D; ++d) load_col<G>(B[d], V, ldv, min(d, j), rc);
+  for (int d = 0; d < D; ++d) load_col<G>(B[d], Vr, ldv, min(d, j), rc);
 #pragma unroll
   for (int i = 0; i < JU; ++i) {
-    mgs_step<G, U, NT>(n, i, j, w, B[i % D], H, ldh, sh, lds_col, sHc);
+    mgs_step<G, U, NT, TAIL>(n, i, j, w, B[i % D], H, ldh, sh, lds_col, sHc);
     if (i == j) goto orthogonal;
-    load_col<G>(B[i % D], V, ldv, min(i + D, j), rc);
+    load_col<G>(B[i % D], Vr, ldv, min(i + D, j), rc);
   }
   for (int i = JU; i <= j; ++i) {
-    double Bt[G];
-    load_col<G>(Bt, V, ldv, i, rc);
-    mgs_step<G, U, NT>(n, i, j, w, Bt, H, ldh, sh, lds_col, sHc);
+    VT Bt[G];
+    load_col<G>(Bt, Vr, ldv, i, rc);
+    mgs_step<G, U, NT, TAIL>(n, i, j, w, Bt, H, ldh, sh, lds_col, sHc);
   }
 orthogonal:
   double acc = 0.0;
@@ -182,29 +191,48 @@ orthogonal:
 #pragma unroll
   for (int t = 0; t < G; ++t) {
     const int r = tid + t * NT;
-    if (r < n) vnx[r] = round_c<U>(w[t] / hn);
+    if (r < n) {
+      const double v = round_c<U>(w[t] / hn);
+      vnx[r] = v;
+      if constexpr (U != P_FP64) Vf[(size_t)(j + 1) * ldv + r] = (float)v;
+    }
+  }
+}
+
+template <int G, int D, int NT, bool TAIL>
+static void launch_arnoldi_t(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
+                             double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
+  switch (u) {
+    case P_FP16:
+      k_arnoldi<G, P_FP16, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st);
+      break;
+    case P_BF16:
+      k_arnoldi<G, P_BF16, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st);
+      break;
+    case P_FP32:
+      k_arnoldi<G, P_FP32, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st);
+      break;
+    default:
+      k_arnoldi<G, P_FP64, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st);
+      break;
   }
 }
 
 template <int G, int D, int NT>
-static void launch_arnoldi_g(hipStream_t s, int n, int j, double* V, int ldv, const double* w, double* H, int ldh,
+static void launch_arnoldi_g(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
                              double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
-  switch (u) {
-    case P_FP16: k_arnoldi<G, P_FP16, D, NT><<<1, NT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    case P_BF16: k_arnoldi<G, P_BF16, D, NT><<<1, NT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    case P_FP32: k_arnoldi<G, P_FP32, D, NT><<<1, NT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-    default: k_arnoldi<G, P_FP64, D, NT><<<1, NT, 0, s>>>(n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, st); break;
-  }
+  if (n == G * NT) launch_arnoldi_t<G, D, NT, false>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else launch_arnoldi_t<G, D, NT, true>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
 }
 
 // values per thread G, basis vectors in flight D, threads NT (see above)
-static void launch_arnoldi(hipStream_t s, int n, int j, double* V, int ldv, const double* w, double* H, int ldh,
+static void launch_arnoldi(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
                            double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
-  if (n <= 512) launch_arnoldi_g<1, 8, 512>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else if (n <= 1024) launch_arnoldi_g<2, 8, 512>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else if (n <= 2048) launch_arnoldi_g<4, 8, 512>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else if (n <= 4096) launch_arnoldi_g<4, 8, 1024>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else launch_arnoldi_g<8, 2, 1024>(s, n, j, V, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  if (n <= 512) launch_arnoldi_g<1, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else if (n <= 1024) launch_arnoldi_g<2, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else if (n <= 2048) launch_arnoldi_g<4, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else if (n <= 4096) launch_arnoldi_g<8, 4, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+  else launch_arnoldi_g<8, 2, 1024>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
 }
 
 // y = R^{-1} g (upper triangular from the rotated Hessenberg), one wave,
@@ -279,7 +307,8 @@ int gmres(Ctx& c, GmresWork& gw, const GmresOp& op, const double* rhat, double t
   for (;;) {
     int m = restart > 0 ? restart : k_cap;
     if (m > k_cap - k) m = k_cap - k;
-    k_gmres_start<<<1, GNT, 0, c.stream>>>(n, gw.resid, gw.V, gw.g, gw.beta0, first ? 1 : 0, u, st);
+    k_gmres_start<<<1, GNT, 0, c.stream>>>(n, gw.resid, gw.V, u == P_FP64 ? nullptr : gw.Vf, gw.g, gw.beta0,
+                                           first ? 1 : 0, u, st);
     HIP_CHECK(hipGetLastError());
     first = false;
     int jdone = 0;
@@ -287,7 +316,7 @@ int gmres(Ctx& c, GmresWork& gw, const GmresOp& op, const double* rhat, double t
     for (int it = 0; it < m; ++it) {
       rc = op.apply_full(c, gw.V + (size_t)it * ldv, gw.w, &st->done);
       if (rc) return rc;
-      MSIR_TIMED(c, MSIR_T_ARNOLDI, launch_arnoldi(c.stream, n, it, gw.V, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g,
+      MSIR_TIMED(c, MSIR_T_ARNOLDI, launch_arnoldi(c.stream, n, it, gw.V, gw.Vf, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g,
                                                    gw.beta0, tau, u, st));
       HIP_CHECK(hipGetLastError());
       if ((it + 1) % CHK == 0 || it + 1 == m) {

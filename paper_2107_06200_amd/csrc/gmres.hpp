@@ -15,6 +15,7 @@ struct GmresWork {
   int ncap = 0, mcap = 0;
   double *V = nullptr, *H = nullptr, *cs = nullptr, *sn = nullptr, *g = nullptr, *y = nullptr;
   double *w = nullptr, *resid = nullptr, *delta = nullptr, *dacc = nullptr, *beta0 = nullptr;
+  float* Vf = nullptr;   // float32 copy of the basis (working formats below float64)
   GStatus* status = nullptr;
   GStatus* host_status = nullptr;
   DevBuf buf;

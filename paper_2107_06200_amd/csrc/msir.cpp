@@ -107,13 +107,15 @@ int GmresWork::ensure(Ctx& c, int n, int m) {
   mcap = std::max(m, mcap);
   const size_t nv = (size_t)(mcap + 1) * ncap;
   const size_t nh = (size_t)(mcap + 1) * (mcap + 1);
-  const size_t total = nv + nh + 4 * (size_t)(mcap + 2) + 4 * (size_t)ncap + 8 + 8;
+  const size_t nvf = (nv + 1) / 2;   // float copy of the basis, in doubles
+  const size_t total = nv + nvf + nh + 4 * (size_t)(mcap + 2) + 4 * (size_t)ncap + 8 + 8;
   void* p = nullptr;
   if (c.alloc(&p, total * sizeof(double))) return MSIR_ERR_ALLOC;
   buf.p = p;
   buf.bytes = total * sizeof(double);
   double* q = (double*)p;
   V = q; q += nv;
+  Vf = (float*)q; q += nvf;
   H = q; q += nh;
   cs = q; q += mcap + 2;
   sn = q; q += mcap + 2;
@@ -138,6 +140,7 @@ void GmresWork::free_all(Ctx& c) {
   if (host_status) (void)hipHostFree(host_status);
   host_status = nullptr;
   V = nullptr;
+  Vf = nullptr;
   ncap = mcap = 0;
 }
 
