@@ -312,21 +312,30 @@ int gmres(Ctx& c, GmresWork& gw, const GmresOp& op, const double* rhat, double t
     HIP_CHECK(hipGetLastError());
     first = false;
     int jdone = 0;
-    const int CHK = 8;
+    // the host reads the status after 8, 16, 32, ... iterations and at the end of the
+    // cycle; launches after convergence are no-ops on the device, so at most as many
+    // iterations are skipped as have run, while a long cycle costs few host round trips
+    int next_check = 8;
+    bool fresh = false;   // host_status read after the last launch
     for (int it = 0; it < m; ++it) {
+      fresh = false;
       rc = op.apply_full(c, gw.V + (size_t)it * ldv, gw.w, &st->done);
       if (rc) return rc;
       MSIR_TIMED(c, MSIR_T_ARNOLDI, launch_arnoldi(c.stream, n, it, gw.V, gw.Vf, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g,
                                                    gw.beta0, tau, u, st));
       HIP_CHECK(hipGetLastError());
-      if ((it + 1) % CHK == 0 || it + 1 == m) {
+      if (it + 1 == next_check || it + 1 == m) {
+        next_check *= 2;
         HIP_CHECK(hipMemcpyAsync(gw.host_status, st, sizeof(GStatus), hipMemcpyDeviceToHost, c.stream));
         HIP_CHECK(hipStreamSynchronize(c.stream));
+        fresh = true;
         if (gw.host_status->done) break;
       }
     }
-    HIP_CHECK(hipMemcpyAsync(gw.host_status, st, sizeof(GStatus), hipMemcpyDeviceToHost, c.stream));
-    HIP_CHECK(hipStreamSynchronize(c.stream));
+    if (!fresh) {
+      HIP_CHECK(hipMemcpyAsync(gw.host_status, st, sizeof(GStatus), hipMemcpyDeviceToHost, c.stream));
+      HIP_CHECK(hipStreamSynchronize(c.stream));
+    }
     jdone = gw.host_status->jcount;
     const bool stop = gw.host_status->done != 0;
     k_lsq<<<1, 64, 0, c.stream>>>(gw.H, ldh, gw.g, gw.y, st);

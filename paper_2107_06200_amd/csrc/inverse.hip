@@ -6,13 +6,15 @@
 // u_f factors, and then every application is two matrix-vector products that
 // stream the triangles at full memory bandwidth.
 //
-// X = L^{-1} (unit lower) by block rows of 64, starting from X = I:
-//   X_k,: <- inv(L_kk) X_k,:            (diagonal block inverse, 64 x 64)
-//   X_{>k},: <- X_{>k},: - L_{>k,k} X_k,:  (rank-64 update on the matrix cores'
-//                                            vector path, float64 FMA)
-// Y = U^{-1} the same way from the last block row upwards.  Only the nonzero
-// column range of each block row is touched.  Cost: n^3/3 float64 multiply-adds
-// per triangle.
+// X = L^{-1} (unit lower) by block rows of 64, top down:
+//   X_kk = inv(L_kk)                        (diagonal blocks, all at once)
+//   for k = 0, 1, ...:  X_{>k},: <- X_{>k},: - L_{>k,k} X_k,:   (rank-64 update)
+//                       X_{k+1},: <- X_{k+1,k+1} X_{k+1},:        (block row k+1 done)
+// Y = U^{-1} the same way from the last block row upwards.  One launch per step k
+// covers both triangles: every 64 x 64 tile of the update is one workgroup, and the
+// tiles of the next block row apply the diagonal-block inverse in the same
+// workgroup, so a step is a single launch.  Only the nonzero column range of each
+// block row is touched.  Cost: n^3/3 float64 multiply-adds per triangle.
 #include "common.hpp"
 #include "msir_internal.hpp"
 
@@ -21,10 +23,11 @@ namespace msir {
 constexpr int IB = 64;
 
 // Inverse of one 64x64 diagonal block of L (unit lower, UPPER=false) or U
-// (UPPER=true), float64, column by column (thread c solves T x = e_c).
+// (UPPER=true), float64, column by column (thread c solves T x = e_c), written to
+// the diagonal block of the n x n result Z (ld n).
 template <int P, bool UPPER>
 __global__ __launch_bounds__(64) void k_trtri_diag(int n, const typename Store<P>::T* __restrict__ W, int ldw,
-                                                   double* __restrict__ dinv) {
+                                                   double* __restrict__ Z) {
   const int blk = blockIdx.x;
   const int r0 = blk * IB;
   const int rows = min(IB, n - r0);
@@ -59,65 +62,12 @@ __global__ __launch_bounds__(64) void k_trtri_diag(int n, const typename Store<P
       x[i] = (i < rows) ? acc / T[i][i] : 0.0;
     }
   }
-  double* d = dinv + (size_t)blk * IB * IB;
+  if (c < rows) {
+    double* d = Z + (size_t)(r0 + c) * n + r0;
 #pragma unroll
-  for (int i = 0; i < IB; ++i) d[(size_t)c * IB + i] = (i < rows && c < rows) ? x[i] : 0.0;
-}
-
-// C[M x N] = beta C + alpha A[M x K] B[K x N]; A of storage type TA, B and C float64,
-// all column-major.  64 x 64 tile per workgroup, 4 x 4 outputs per thread, K in
-// steps of 16 staged through LDS.
-template <int PA>
-__global__ __launch_bounds__(256) void k_gemm_d(int M, int N, int K, double alpha,
-                                                const typename Store<PA>::T* __restrict__ A,
-                                                int lda, const double* __restrict__ B, int ldb, double beta,
-                                                double* __restrict__ C, int ldc) {
-  const int tid = threadIdx.x;
-  const int tx = tid & 15, ty = tid >> 4;
-  const int r0 = blockIdx.x * 64, c0 = blockIdx.y * 64;
-  __shared__ double sA[16][64 + 1];
-  __shared__ double sB[16][64 + 1];
-  double acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.0;
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int i = e & 63, k = e >> 6;
-      const int r = r0 + i, kk = k0 + k;
-      sA[k][i] = (r < M && kk < K) ? Store<PA>::to_d(A[(size_t)kk * lda + r]) : 0.0;
-    }
-    for (int e = tid; e < 16 * 64; e += 256) {
-      const int k = e & 15, q = e >> 4;
-      const int c = c0 + q, kk = k0 + k;
-      sB[k][q] = (c < N && kk < K) ? B[(size_t)c * ldb + kk] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < 16; ++k) {
-      double a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = sA[k][ty + 16 * i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = sB[k][tx + 16 * j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __fma_rn(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
+    for (int i = 0; i < IB; ++i)
+      if (i < rows) d[i] = x[i];
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
-      if (r < M && c < N) {
-        double* cp = C + (size_t)c * ldc + r;
-        *cp = (beta == 0.0) ? alpha * acc[i][j] : __fma_rn(alpha, acc[i][j], beta * (*cp));
-      }
-    }
 }
 
 __global__ __launch_bounds__(256) void k_identity(int n, double* __restrict__ X, int ldx) {
@@ -126,58 +76,171 @@ __global__ __launch_bounds__(256) void k_identity(int n, double* __restrict__ X,
   if (i < n) X[(size_t)j * ldx + i] = (i == j) ? 1.0 : 0.0;
 }
 
-// copy a rows x cols block (column-major) src -> dst
-__global__ __launch_bounds__(256) void k_copy_block(int rows, int cols, const double* __restrict__ src, int lds,
-                                                    double* __restrict__ dst, int ldd) {
-  const int i = blockIdx.x * 256 + threadIdx.x;
-  const int j = blockIdx.y;
-  if (i < rows && j < cols) dst[(size_t)j * ldd + i] = src[(size_t)j * lds + i];
-}
+// Tiles of step t: the lower part (k = t) has block rows I in (k, nb) and column
+// blocks J in [0, k]; the upper part (k = nb - 1 - t) has block rows I in [0, k) and
+// column blocks J in [k, nb).
+__host__ __device__ inline int inv_step_tiles_lower(int nb, int t) { return (nb - 1 - t) * (t + 1); }
+__host__ __device__ inline int inv_step_tiles_upper(int nb, int t) { return (nb - 1 - t) * (t + 1); }
 
-template <int PA>
-static void gemm_d(Ctx& c, int M, int N, int K, double alpha, const typename Store<PA>::T* A, int lda,
-                   const double* B, int ldb, double beta, double* C, int ldc) {
-  if (M <= 0 || N <= 0) return;
-  dim3 g((M + 63) / 64, (N + 63) / 64);
-  k_gemm_d<PA><<<g, 256, 0, c.stream>>>(M, N, K, alpha, A, lda, B, ldb, beta, C, ldc);
+// One step of both inverses.  Tile (I, J) of Z (X or Y), K = block k:
+//   C = Z_IJ - F_Ik Z_kJ           (F = the stored factor, converted to float64)
+//   if I is the next block row:  C = Z_II C   (Z_II = the diagonal-block inverse)
+// Each product is a float64 multiply-add chain over the 64 inner indices in
+// increasing order, subtracted from Z_IJ with one rounding.  256 threads, 4 x 4
+// outputs each (rows lx + 16a, columns ly + 16b); every load of the tile (factor
+// block, Z_kJ, Z_IJ and, for the next block row, Z_II) is issued before any is used.
+template <int P>
+__global__ __launch_bounds__(256) void k_inv_step(int n, int nb, int t, const typename Store<P>::T* __restrict__ W,
+                                                  int ldw, double* __restrict__ X, double* __restrict__ Y) {
+  typedef typename Store<P>::T ST;
+  int id = blockIdx.x;
+  const int nl = inv_step_tiles_lower(nb, t);
+  bool upper;
+  int I, J, k;
+  if (id < nl) {
+    upper = false;
+    k = t;
+    I = k + 1 + id / (k + 1);
+    J = id % (k + 1);
+  } else {
+    id -= nl;
+    upper = true;
+    k = nb - 1 - t;
+    const int nc = nb - k;
+    I = id / nc;
+    J = k + id % nc;
+  }
+  double* Z = upper ? Y : X;
+  const bool fin = upper ? (I == k - 1) : (I == k + 1);
+  const int r0 = I * IB, c0 = J * IB, k0 = k * IB;
+  const int rows = min(IB, n - r0), cols = min(IB, n - c0), kd = min(IB, n - k0);
+  const int tid = threadIdx.x;
+  const int lx = tid & 15, ly = tid >> 4;
+  __shared__ double sA[IB][IB + 1];   // sA[q][i] = F(r0 + i, k0 + q), later Z_II(i, q)
+  __shared__ double sB[IB][IB + 1];   // sB[j][q] = Z(k0 + q, c0 + j), later C(q, j)
+  // 1. all loads in flight: 16 elements each of the factor block, Z_kJ, Z_IJ (own
+  // outputs) and, for the next block row, Z_II
+  ST fa[16];
+  double fb[16], cz[4][4], fd[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    const int i = e & 63, kk = e >> 6;
+    fa[q] = W[(size_t)(k0 + min(kk, kd - 1)) * ldw + r0 + min(i, rows - 1)];
+    fb[q] = Z[(size_t)(c0 + min(kk, cols - 1)) * n + k0 + min(i, kd - 1)];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+      cz[a][b] = Z[(size_t)(c0 + min(ly + 16 * b, cols - 1)) * n + r0 + min(lx + 16 * a, rows - 1)];
+  if (fin) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      const int i = e & 63, kk = e >> 6;
+      fd[q] = Z[(size_t)(r0 + min(kk, rows - 1)) * n + r0 + min(i, rows - 1)];
+    }
+  }
+  // 2. stage the factor block and Z_kJ (zero outside the matrix)
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q;
+    const int i = e & 63, kk = e >> 6;
+    sA[kk][i] = (i < rows && kk < kd) ? Store<P>::to_d(fa[q]) : 0.0;
+    sB[kk][i] = (i < kd && kk < cols) ? fb[q] : 0.0;   // element (row i of block k, column kk)
+  }
+  __syncthreads();
+  // 3. C = Z_IJ - F_Ik Z_kJ
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 8
+  for (int q = 0; q < IB; ++q) {
+    double fa4[4], fb4[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) fa4[a] = sA[q][lx + 16 * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) fb4[b] = sB[ly + 16 * b][q];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = __fma_rn(fa4[a], fb4[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cz[a][b] = __fma_rn(-1.0, acc[a][b], cz[a][b]);
+  if (fin) {
+    // 4. C = Z_II C: C goes to sB (transposed like Z_kJ), Z_II to sA
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) sB[ly + 16 * b][lx + 16 * a] = (lx + 16 * a < rows) ? cz[a][b] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      const int i = e & 63, kk = e >> 6;
+      sA[kk][i] = (i < rows && kk < rows) ? fd[q] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+#pragma unroll 8
+    for (int q = 0; q < IB; ++q) {
+      double fa4[4], fb4[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fa4[a] = sA[q][lx + 16 * a];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) fb4[b] = sB[ly + 16 * b][q];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __fma_rn(fa4[a], fb4[b], acc[a][b]);
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cz[a][b] = acc[a][b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      const int r = lx + 16 * a, cc = ly + 16 * b;
+      if (r < rows && cc < cols) Z[(size_t)(c0 + cc) * n + r0 + r] = cz[a][b];
+    }
 }
 
 template <int P>
-static int tri_inverses_p(Ctx& c, int n, const void* Wv, int ldw, double* X, double* Y, double* T, double* dinv) {
+static int tri_inverses_p(Ctx& c, int n, const void* Wv, int ldw, double* X, double* Y) {
   typedef typename Store<P>::T ST;
   const ST* W = (const ST*)Wv;
-  const int nblk = (n + IB - 1) / IB;
+  const int nb = (n + IB - 1) / IB;
   dim3 gi((n + 255) / 256, n);
-  // L^{-1}
-  k_trtri_diag<P, false><<<nblk, 64, 0, c.stream>>>(n, W, ldw, dinv);
   k_identity<<<gi, 256, 0, c.stream>>>(n, X, n);
-  for (int k = 0; k < nblk; ++k) {
-    const int r0 = k * IB, rows = std::min(IB, n - r0), cols = r0 + rows;
-    k_copy_block<<<dim3(1, cols), 256, 0, c.stream>>>(rows, cols, X + r0, n, T, IB);
-    gemm_d<P_FP64>(c, rows, cols, rows, 1.0, dinv + (size_t)k * IB * IB, IB, T, IB, 0.0, X + r0, n);
-    gemm_d<P>(c, n - r0 - rows, cols, rows, -1.0, W + (size_t)r0 * ldw + r0 + rows, ldw, X + r0, n, 1.0,
-               X + r0 + rows, n);
-  }
-  // U^{-1}
-  k_trtri_diag<P, true><<<nblk, 64, 0, c.stream>>>(n, W, ldw, dinv);
   k_identity<<<gi, 256, 0, c.stream>>>(n, Y, n);
-  for (int k = nblk - 1; k >= 0; --k) {
-    const int r0 = k * IB, rows = std::min(IB, n - r0), cols = n - r0;
-    k_copy_block<<<dim3(1, cols), 256, 0, c.stream>>>(rows, cols, Y + (size_t)r0 * n + r0, n, T, IB);
-    gemm_d<P_FP64>(c, rows, cols, rows, 1.0, dinv + (size_t)k * IB * IB, IB, T, IB, 0.0, Y + (size_t)r0 * n + r0, n);
-    gemm_d<P>(c, r0, cols, rows, -1.0, W + (size_t)r0 * ldw, ldw, Y + (size_t)r0 * n + r0, n, 1.0,
-               Y + (size_t)r0 * n, n);
+  k_trtri_diag<P, false><<<nb, 64, 0, c.stream>>>(n, W, ldw, X);
+  k_trtri_diag<P, true><<<nb, 64, 0, c.stream>>>(n, W, ldw, Y);
+  for (int t = 0; t + 1 < nb; ++t) {
+    const int tiles = inv_step_tiles_lower(nb, t) + inv_step_tiles_upper(nb, t);
+    k_inv_step<P><<<tiles, 256, 0, c.stream>>>(n, nb, t, W, ldw, X, Y);
   }
   HIP_CHECK(hipGetLastError());
   return 0;
 }
 
-int tri_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* X, double* Y, double* T, double* dinv) {
+int tri_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* X, double* Y) {
   switch (prec) {
-    case P_FP16: return tri_inverses_p<P_FP16>(c, n, W, ldw, X, Y, T, dinv);
-    case P_BF16: return tri_inverses_p<P_BF16>(c, n, W, ldw, X, Y, T, dinv);
-    case P_FP32: return tri_inverses_p<P_FP32>(c, n, W, ldw, X, Y, T, dinv);
-    case P_FP64: return tri_inverses_p<P_FP64>(c, n, W, ldw, X, Y, T, dinv);
+    case P_FP16: return tri_inverses_p<P_FP16>(c, n, W, ldw, X, Y);
+    case P_BF16: return tri_inverses_p<P_BF16>(c, n, W, ldw, X, Y);
+    case P_FP32: return tri_inverses_p<P_FP32>(c, n, W, ldw, X, Y);
+    case P_FP64: return tri_inverses_p<P_FP64>(c, n, W, ldw, X, Y);
   }
   return -3;
 }

@@ -228,7 +228,7 @@ struct msir_handle {
   Ctx c;
   GmresWork gw;
   FactorState f;
-  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, dinv, Xd, Yd, Xf, Yf, Tinv;
+  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Xd, Yd, Xf, Yf;
   bool inv64 = false, inv32 = false;  // inverses of the current factorization are valid
   double* dev_small = nullptr;   // device scalars
   double* host_small = nullptr;  // pinned host scalars
@@ -348,10 +348,8 @@ static int ensure_inverses(msir_handle* h, int n, int p, const void** X, const v
   if (!h->inv64) {
     double* Xd = (double*)c.grow(h->Xd, (size_t)n * n * sizeof(double));
     double* Yd = (double*)c.grow(h->Yd, (size_t)n * n * sizeof(double));
-    double* T = (double*)c.grow(h->Tinv, (size_t)64 * n * sizeof(double));
-    double* dv = (double*)c.grow(h->dinv, (size_t)((n + 63) / 64 + 1) * 64 * 64 * sizeof(double));
-    if (!Xd || !Yd || !T || !dv) return MSIR_ERR_ALLOC;
-    int rc = tri_inverses(c, n, h->f.prec, h->f.W, n, Xd, Yd, T, dv);
+    if (!Xd || !Yd) return MSIR_ERR_ALLOC;
+    int rc = tri_inverses(c, n, h->f.prec, h->f.W, n, Xd, Yd);
     if (rc) return rc;
     h->inv64 = true;
     h->inv32 = false;
@@ -460,8 +458,8 @@ int msir_destroy(msir_handle* h) {
   (void)hipStreamSynchronize(h->c.stream);
   Ctx& c = h->c;
   DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.part_x, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
-                    &c.tmp_scalar, &c.moved, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
-                    &h->tmp2, &h->dinv, &h->Xd, &h->Yd, &h->Xf, &h->Yf, &h->Tinv};
+                    &c.tmp_scalar, &c.moved, &c.tr_part, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
+                    &h->tmp2, &h->Xd, &h->Yd, &h->Xf, &h->Yf};
   for (DevBuf* b : bufs) c.release(b->p, b->bytes);
   if (h->f.W) c.release(h->f.W, h->f.Wbytes);
   if (h->f.rinv) c.release(h->f.rinv, h->f.vec_bytes);

@@ -28,7 +28,7 @@ struct Ctx {
   unsigned epoch = 0;
   double* scalars = nullptr;          // 64 device doubles for small results
   double* host_pinned = nullptr;      // 64 pinned host doubles
-  DevBuf part_hi, part_lo, part_x, r_hi, r_lo, mon_part, flags, yfwd, xbwd, tmp_scalar, moved, tr_part, tr_cnt;
+  DevBuf part_hi, part_lo, part_x, r_hi, r_lo, mon_part, flags, yfwd, xbwd, tmp_scalar, moved, tr_part;
   static constexpr int kMaxBlocks = 4096;
   int last_err = 0;
 
@@ -116,8 +116,8 @@ int trsv(Ctx& c, const TrsvArgs& a);
 int trsv_check(Ctx& c, unsigned* out);
 
 // Explicit inverses X = L^{-1}, Y = U^{-1} (float64, n x n, column-major, ld n) of the
-// factors stored in W; T: 64 x n float64 scratch; dinv: (n/64 + 1) * 64 * 64 float64.
-int tri_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* X, double* Y, double* T, double* dinv);
+// factors stored in W (entries outside the triangles are zero).
+int tri_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* X, double* Y);
 int square_to_f32(Ctx& c, int n, const double* X, float* Xf);
 // y = round_p(oscale_i sum_j T_ij xin_j): T triangular (tri 1 lower, 2 upper) stored in
 // store_prec (FP32 or FP64); xin_j = perm ? R[perm[j]] x[perm[j]] : x[j] (R may be
@@ -167,7 +167,6 @@ int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au
                  const double* Rp, int inv_prec, const void* X, const void* Y, double mu, const double* S, int u,
                  double* out, const int* skip);
 int gather(Ctx& c, int n, const double* src, const int* idx, double* dst);
-int diag_block_inverses(Ctx& c, int n, int prec, const void* W, int ldw, double* dinv);
 size_t diag_inv_doubles(int n);
 
 }  // namespace msir
