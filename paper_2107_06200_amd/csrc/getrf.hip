@@ -17,8 +17,10 @@
 //     Ties go to the lowest position, NaN never wins, a zero pivot column is
 //     recorded in info and left unscaled.  Multipliers use the correctly
 //     rounded reciprocal of the pivot; the rank-1 update uses fused
-//     multiply-adds.  The panel is written back to its final row positions,
-//     rounded to u_f.
+//     multiply-adds, with multiplier 0 (no per-element select) for the rows
+//     that take no part; each pivot row's U entries are saved in LDS when it is
+//     chosen.  The panel is written back to its final row positions, rounded to
+//     u_f.
 //  2. k_update (one workgroup per 32-column strip): applies the panel's row
 //     interchanges to the strip; for strips right of the panel it solves
 //     U12 = L11^{-1} A12 (forward substitution, fused multiply-adds, rows in
@@ -156,6 +158,7 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
   const int m = n - j0;
   __shared__ AT srow[2][PNW][NB];
   __shared__ K skey[2][PNW];
+  __shared__ AT sU[NB][NB];   // row c of U (entries c..NB-1), saved when it is chosen
 
   AT a[R][NB];
   int pos[R];
@@ -226,6 +229,13 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
       // interchange = relabelling of positions c and gp
 #pragma unroll
       for (int s = 0; s < R; ++s) pos[s] = (pos[s] == c) ? gp : ((pos[s] == gp) ? c : pos[s]);
+      // the row now at position c is final from column c on (its U entries): keep a copy
+#pragma unroll
+      for (int s = 0; s < R; ++s)
+        if (valid[s] && pos[s] == c) {
+#pragma unroll
+          for (int k = c; k < NB; ++k) sU[c][k] = a[s][k];
+        }
       if (gv > AT(0)) {
         // pivot row: lane k reads entry k, every entry is then broadcast by readlane
         const AT prow = lane < NB ? srow[buf][gw][lane] : AT(0);
@@ -238,27 +248,32 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
           l[s] = a_mul(a[s][c], rcp);
           a[s][c] = act[s] ? l[s] : a[s][c];
         }
-        // columns k >= jb hold zeros (loaded as such), so updating them is harmless
+        // columns k >= jb hold zeros (loaded as such), so updating them is harmless.
+        // Rows that take no part (pivot rows, rows past the panel) get the multiplier
+        // 0 and pass through the multiply-adds; their values are not used again
+        // except the pivot rows' U entries, which are written back from sU.
+        AT le[R];
+#pragma unroll
+        for (int s = 0; s < R; ++s) le[s] = act[s] ? l[s] : AT(0);
 #pragma unroll
         for (int k = c + 1; k < NB; ++k) {
           const AT pk = bcast_a(prow, k);
 #pragma unroll
-          for (int s = 0; s < R; ++s) {
-            const AT t = a_fma(-l[s], pk, a[s][k]);
-            a[s][k] = act[s] ? t : a[s][k];
-          }
+          for (int s = 0; s < R; ++s) a[s][k] = a_fma(-le[s], pk, a[s][k]);
         }
       }
     }
   }
-  // write the panel back to the final row positions, rounded to u_f
+  // write the panel back to the final row positions, rounded to u_f (pivot rows: L
+  // entries from the registers, U entries from sU)
+  __syncthreads();
 #pragma unroll
   for (int s = 0; s < R; ++s) {
     if (valid[s]) {
       const int q = pos[s];
 #pragma unroll
       for (int k = 0; k < NB; ++k)
-        if (k < jb) W[(size_t)(j0 + k) * ldw + j0 + q] = from_a<P>(a[s][k]);
+        if (k < jb) W[(size_t)(j0 + k) * ldw + j0 + q] = from_a<P>((q < jb && k >= q) ? sU[q][k] : a[s][k]);
     }
   }
   // list of rows that changed position: moved[0] = count, then (dst, src) pairs
