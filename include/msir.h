@@ -50,8 +50,13 @@ typedef enum { MSIR_FP16 = 0, MSIR_BF16 = 1, MSIR_FP32 = 2, MSIR_FP64 = 3, MSIR_
  * (eq. for the normwise error estimate).  BACKWARD: normwise backward error of
  * the iterate (inf-norm, residual in u_r) <= tol_nbe, tested at every residual.
  * TRUE: forward error (needs x_true) and normwise backward error <= the initial u,
- * the protocol of the paper's experiments (Sec. 3).                             */
-typedef enum { MSIR_CONV_ESTIMATE = 0, MSIR_CONV_BACKWARD = 1, MSIR_CONV_TRUE = 2 } msir_conv;
+ * the protocol of the paper's experiments (Sec. 3).  COMPONENTWISE: the
+ * componentwise relative backward error max_i |b - A x|_i / (|A||x| + |b|)_i
+ * (Sec. 2.1.2 measures; Sec. 2.1.1 notes componentwise measures as an
+ * alternative test) <= tol_nbe, tested where BACKWARD tests; |b - A x| from a
+ * double-double residual, |A||x| + |b| in float64.                               */
+typedef enum { MSIR_CONV_ESTIMATE = 0, MSIR_CONV_BACKWARD = 1, MSIR_CONV_TRUE = 2,
+               MSIR_CONV_COMPONENTWISE = 3 } msir_conv;
 
 /* Scaling before a half-precision LU (Sec. 2.1.2).  AUTO: unscaled first, and
  * if the factors hold Inf/NaN, retry with two-sided power-of-two equilibration
@@ -67,11 +72,12 @@ typedef struct {
     int    i_max;          /* maximum refinement steps of each variant (>= 1)           */
     double tau;            /* GMRES relative preconditioned residual tolerance (> 0);
                               <= 0 selects 1e-6 for u = fp32 and 1e-10 for u = fp64   */
-    double rho_thresh;     /* stopping parameter rho_thresh in (0, 1): 0.5 cautious  */
+    double rho_thresh;     /* stopping parameter rho_thresh in (0, 1): 0.5 cautious,
+                              0.9 aggressive (Sec. 2.1.1)                            */
     double k_max;          /* GMRES iterations per step; <= 0 selects 0.1 n           */
     int    restart;        /* GMRES restart length, 0 = none                          */
     msir_conv conv;        /* convergence detection mode                              */
-    double tol_nbe;        /* tolerance of MSIR_CONV_BACKWARD                         */
+    double tol_nbe;        /* tolerance of MSIR_CONV_BACKWARD and _COMPONENTWISE      */
     msir_scale scaling;    /* Sec. 2.1.2 scaling policy                               */
     int    nb;             /* LU panel width; 0 = automatic (see msir_nb_auto)        */
     int    max_steps;      /* global cap on refinement steps (safety)                 */

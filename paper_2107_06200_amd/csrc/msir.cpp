@@ -779,6 +779,7 @@ int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* d
   if (P.ur != MSIR_FP64 && P.ur != MSIR_DD) return -8;
   if (P.ux != MSIR_FP64 && P.ux != P.u) return -8;
   if (P.i_max < 1 || !(P.rho_thresh > 0) || P.restart < 0 || P.max_steps < 1) return -8;
+  if (P.conv < MSIR_CONV_ESTIMATE || P.conv > MSIR_CONV_COMPONENTWISE) return -8;
   if (P.conv == MSIR_CONV_TRUE && !dxt) return -7;
   if (P.nb != 0 && !nb_ok(n, P.uf, P.nb)) return -8;
   if (P.lu_update != MSIR_LU_MFMA && P.lu_update != MSIR_LU_FMA) return -8;
@@ -897,6 +898,17 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
   auto errors_ok = [&](const double* xx, double s, double xn_, bool* ok) -> int {
     *ok = false;
     if (P.conv == MSIR_CONV_BACKWARD) { *ok = nbe_of(s, xn_) <= P.tol_nbe; return 0; }
+    if (P.conv == MSIR_CONV_COMPONENTWISE) {
+      // [0] max |r_i| (double-double residual), [1] max_i |r_i| / (|A||x| + |b|)_i
+      double* ce = ds + 58;
+      int r2 = backward_errors(c, n, dA, lda, xx, db, ce);
+      if (r2) return r2;
+      r2 = sync_read(h, ce, 2);
+      if (r2) return r2;
+      const double cb = h->host_small[1];
+      *ok = cb <= P.tol_nbe;   // false for NaN
+      return 0;
+    }
     if (P.conv == MSIR_CONV_TRUE) {
       double fe;
       int r2 = ferr_of(xx, &fe);

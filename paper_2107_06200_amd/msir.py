@@ -19,7 +19,7 @@ _LIB = None
 
 PREC = {"fp16": 0, "bf16": 1, "fp32": 2, "fp64": 3, "dd": 4}
 PREC_NAME = {v: k for k, v in PREC.items()}
-CONV = {"estimate": 0, "backward": 1, "true": 2}
+CONV = {"estimate": 0, "backward": 1, "true": 2, "componentwise": 3}
 SCALE = {"never": 0, "auto": 1, "always": 2, "cols": 3}
 TORCH_DTYPE = {0: torch.float16, 1: torch.bfloat16, 2: torch.float32, 3: torch.float64}
 STATUS = {0: "converged", 1: "not converged", 2: "singular"}

@@ -16,6 +16,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
+from oracle import metrics as OMET
 from oracle import msir as OM
 from paper_2107_06200_amd import workloads as WL
 
@@ -168,3 +169,25 @@ def test_multi_rhs_and_batched_match_single(M, h):
         assert o.nbe <= 1e-15
         xi, _, _, _ = M.solve(h, M.colmajor(torch.from_numpy(np.asfortranarray(a)).to(DEV)), torch.from_numpy(b).to(DEV))
         assert torch.equal(xi, xg)
+
+
+@pytest.mark.parametrize("rho", [0.5, 0.9])
+def test_rho_thresh_cautious_and_aggressive(M, h, rho):
+    # Sec. 2.1.1: cautious 0.5 and aggressive 0.9; on this system the two leave SIR at
+    # different steps (oracle: "2, (3,3,3)" and "10, (2,3)")
+    A, x, b = WL.randsvd(100, 3e3, 2, WL.rng_for(31, 0))
+    check(M, h, A, x, b, 3e3, uf="fp16", u="fp32", ur="fp64", k_max=20, rho_thresh=rho)
+
+
+@pytest.mark.parametrize("cfg,n,tol", [(1, None, 1e-15), (1, None, 1e-13), (2, 256, 1e-15)])
+def test_componentwise_convergence(M, h, cfg, n, tol):
+    # conv = componentwise: same history as the oracle, and the returned x meets the
+    # componentwise backward error tolerance (GPU figure and host recomputation)
+    A, x, b = WL.config_system(cfg, n=n) if n else WL.config_system(cfg)
+    prm = dict(WL.CONFIGS[cfg]["params"])
+    prm.update(conv="componentwise", tol_nbe=tol)
+    xg, res, hist, rc, ref = run_both(M, h, A, x, b, **prm)
+    print("gpu", M.render(hist), "cbe %.2e" % res.cbe, "| oracle", OM.render(ref.history))
+    assert_same_history(hist, ref)
+    assert rc == 0 and res.cged == 1
+    assert res.cbe <= tol and OMET.cbe(A, xg, b) <= tol

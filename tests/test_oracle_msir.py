@@ -193,3 +193,41 @@ def test_config1_backward_converges():
     res = M.msir(A, b, p, x_true=x)
     assert res.cged and res.nbe <= 1e-15
     assert all(st.stage == M.SIR for st in res.history)
+
+
+def test_script_aggressive_rho_keeps_sir():
+    # Sec. 2.1.1: v = ||d2|| / ||d1|| = 0.6 triggers a switch under the cautious
+    # rho_thresh = 0.5 but not under the aggressive 0.9, so SIR continues
+    items = [("d", 1e-3, -1), ("d", 0.6e-3, -1), ("d", 0.36e-3, -1)] + [("d", 1e-30, 1)] * 40
+    res, s = run_script(list(items), max_steps=3, rho_thresh=0.9)
+    assert s.calls[:3] == [M.SIR, M.SIR, M.SIR]
+    assert not res.history[1].events & M.EV_SWITCH
+    res, s = run_script(list(items), max_steps=3, rho_thresh=0.5)
+    assert s.calls[:3] == [M.SIR, M.SIR, M.SGMRES]
+
+
+def test_aggressive_rho_moves_the_switch():
+    # a system whose SIR ratios lie between 0.5 and 0.9: the cautious setting leaves
+    # SIR on the first ratio >= 0.5, the aggressive one stays for i_max steps
+    A, x, b = WL.randsvd(100, 3e3, 2, WL.rng_for(31, 0))
+    runs = {rho: M.msir(A, b, M.Params(rho_thresh=rho, uf="fp16", u="fp32", ur="fp64", k_max=20), x_true=x)
+            for rho in (0.5, 0.9)}
+    sir = {rho: [st for st in r.history if st.stage == M.SIR] for rho, r in runs.items()}
+    assert sir[0.5][-1].v >= 0.5 and len(sir[0.5]) < 10
+    assert len(sir[0.9]) == 10 and max(st.v for st in sir[0.9]) < 0.9
+    assert all(r.cged and metrics.nbe(A, r.x, b) <= 1e-15 for r in runs.values())
+
+
+def test_componentwise_stops_at_first_iterate_meeting_tolerance():
+    # conv = 'componentwise': the solve ends at the first iterate whose componentwise
+    # backward error (the measure of Sec. 2.1.2, recomputed here by metrics.cbe) is
+    # <= tol; the iterate one step earlier is above it
+    A, x, b = WL.config_system(1)
+    tol = 1e-15
+    full = M.msir(A, b, M.Params(conv="componentwise", tol_nbe=tol), x_true=x)
+    assert full.cged and metrics.cbe(A, full.x, b) <= tol
+    K = len(full.history)
+    prev = M.msir(A, b, M.Params(conv="componentwise", tol_nbe=tol, max_steps=K - 1), x_true=x)
+    assert not prev.cged and metrics.cbe(A, prev.x, b) > tol
+    loose = M.msir(A, b, M.Params(conv="componentwise", tol_nbe=1e-13), x_true=x)
+    assert loose.cged and len(loose.history) <= K
