@@ -166,6 +166,21 @@ MSIR_API int msir_solve(msir_handle* h, int n, const double* dA, int lda, const 
                const double* dx_true, const msir_params* params, msir_result* out,
                msir_step* hist, int hist_cap, int* hist_len);
 
+/* GMRES-IR5: the five-precision GMRES-based refinement of Sec. 1 (u_f, u, u_r,
+ * u_g, u_p), without the multistage controller.  One LU in params->uf (scaling
+ * policy params->scaling), x0 from the factors, then steps: r = b - A x in
+ * params->ur, r_hat = fl_ug(r / ||r||_inf), GMRES in ug with the preconditioned
+ * matrix applied in up (explicit inverses for up in {FP32, FP64}, substitution for
+ * DD), x <- fl_ux(x + fl_ux(||r|| d)).  Stops when the test of params->conv passes,
+ * on a non-finite correction, or after params->i_max steps.  ug: FP32 or FP64,
+ * not more precise than params->u (u_g >= u); up: FP32, FP64 or DD.  With
+ * ug = up = u the steps are SGMRES-IR's (Alg. 3); ug = u, up = u^2 GMRES-IR's
+ * (Alg. 2).  History entries are stage-2 steps of level 0.  Other arguments and
+ * the return value as for msir_solve; -9: ug or up not allowed.                   */
+MSIR_API int msir_gmres_ir5(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
+                   const double* dx_true, const msir_params* params, msir_prec ug, msir_prec up,
+                   msir_result* out, msir_step* hist, int hist_cap, int* hist_len);
+
 /* nrhs right-hand sides sharing one factorization per precision level (the
  * multi-RHS reading of Alg. 4: an independent controller per column; when a
  * column escalates, the higher-precision factorization is computed once and

@@ -342,3 +342,105 @@ def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None):
         return res, x0
     return res
 
+
+
+def gmres_ir5(A, b, params=Params(), ug=None, up=None, x_true=None):
+    """Five-precision GMRES-based refinement (GMRES-IR5 as summarised in Sec. 1).
+
+    One LU factorization in u_f (the scaling policy of ``params``), x0 from the
+    factors, then refinement steps: residual in u_r, the scaled residual rounded to
+    the GMRES working precision u_g, GMRES in u_g with the preconditioned matrix
+    applied in u_p, and the update x <- fl_ux(x + fl_ux(s d)).  There is no switching
+    and no escalation: the solve stops when the convergence test of ``params.conv``
+    passes ('estimate': 0 <= phi <= sqrt(n) u_x after each step; the other modes at
+    every residual), on a non-finite correction, or after i_max steps.  With
+    u_g = u_p = u this is SGMRES-IR (Alg. 3); u_g = u, u_p = u^2 is GMRES-IR (Alg. 2).
+    Steps are recorded as GMRES-IR stage steps of level 0.
+    """
+    A = np.asarray(A, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    n = A.shape[0]
+    P = params
+    uf, u, ur, ux = P.uf, P.u, P.ur, P.ux
+    ug = u if ug is None else ug
+    up = square(u) if up is None else up
+    k_max = 0.1 * n if P.k_max is None else P.k_max
+    tau = P.tau if P.tau is not None else (1e-6 if ug == "fp32" else 1e-10)
+    normA = float(np.abs(A).sum(axis=1).max())
+    normb = float(np.abs(b).max())
+    sqn = math.sqrt(n)
+
+    def nbe_of(s, xx):
+        den = normA * float(np.abs(xx).max()) + normb
+        return s / den if den > 0 else (0.0 if s == 0 else math.inf)
+
+    def errors_ok(xx):
+        rt = ops.residual(A, xx, b, "dd")
+        st = ops.rnorm_inf(rt)
+        if not np.isfinite(st):
+            return False
+        if P.conv == "backward":
+            return nbe_of(st, xx) <= P.tol_nbe
+        if P.conv == "componentwise":
+            num = np.abs(rt[0] + rt[1])
+            den = np.abs(A) @ np.abs(xx) + np.abs(b)
+            with np.errstate(all="ignore"):
+                q = np.where(den > 0, num / den, np.where(num > 0, np.inf, 0.0))
+            return bool(q.max() <= P.tol_nbe)
+        if P.conv == "true":
+            fe = float(np.abs(xx - x_true).max() / np.abs(x_true).max())
+            return fe <= F.u(u) and nbe_of(st, xx) <= F.u(u)
+        return False
+
+    W, piv, info, scal = factor(A, uf, P.scaling, P.nb, P.lu_trailing)
+    ev = EV_SCALED if scal is not None else 0
+    x = lu_solve(W, piv, b, uf, scal)
+    if not np.all(np.isfinite(x)):
+        x = np.zeros(n)
+        ev |= EV_NAN_X0
+    x = F.round_to(x, ux)
+    hist = []
+    cged, status = False, 1
+    dprev, rho_max = math.inf, 0.0
+    for it in range(1, P.i_max + 1):
+        r = ops.residual(A, x, b, ur)
+        s = ops.rnorm_inf(r)
+        nbe_x = nbe_of(s, x) if np.isfinite(s) else math.nan
+        if s == 0.0 or (P.conv != "estimate" and np.isfinite(s) and errors_ok(x)):
+            cged, status = True, 0
+            break
+        rhat = ops.scale_residual(r, s, ug)
+        d, k = gmres(A, W, piv, scal, rhat, ug, up, tau, k_max, P.restart)
+        d = np.asarray(d, dtype=np.float64)
+        if not np.all(np.isfinite(d)):
+            hist.append(Step(0, uf, u, ur, GMRES, it, k, math.nan, math.nan, rho_max, math.nan, s, nbe_x,
+                             ev | EV_NAN_D))
+            break
+        with np.errstate(all="ignore"):
+            x_new = F.round_to(x + F.round_to(s * d, ux), ux)
+            delta = s * float(np.abs(d).max())
+            xn = float(np.abs(x).max())
+            z = delta / xn if xn > 0 else (0.0 if delta == 0 else math.inf)
+            v = delta / dprev if dprev != math.inf else 0.0
+            rho_max = max(rho_max, v)
+            phi = z / (1.0 - rho_max) if rho_max < 1.0 else math.inf
+        dprev = delta
+        x = x_new
+        rec = Step(0, uf, u, ur, GMRES, it, k, z, v, rho_max, phi, s, nbe_x, ev)
+        ev = 0
+        hist.append(rec)
+        if P.conv == "estimate" and 0.0 <= phi <= sqn * F.u(ux):
+            rec.events |= EV_CONVERGED
+            cged, status = True, 0
+            break
+    else:
+        # i_max steps done: the last iterate may still pass the test
+        if P.conv != "estimate" and errors_ok(x):
+            cged, status = True, 0
+    res = Result(x=x, cged=cged, status=status, history=hist, n_lu=1)
+    rr = ops.residual(A, x, b, "dd")
+    res.nbe = float(ops.rnorm_inf(rr) / (normA * float(np.abs(x).max()) + normb)) if np.any(x) else math.nan
+    if x_true is not None:
+        res.ferr = float(np.abs(x - x_true).max() / np.abs(x_true).max())
+    res.final = (uf, u, ur)
+    return res

@@ -1107,6 +1107,272 @@ done:
   return status;
 }
 
+// GMRES-IR5 (the five-precision GMRES-based refinement summarised in Sec. 1): one
+// LU in u_f, x0 from the factors, then refinement steps with the residual in u_r,
+// the scaled residual rounded to u_g, GMRES in u_g with the preconditioned matrix
+// applied in u_p, and the update fl_ux(x + fl_ux(s d)).  No switching, no
+// escalation: the convergence test of P.conv, a non-finite correction or i_max
+// steps end the solve.  Steps are recorded as GMRES-IR stage steps of level 0.
+static int ir5_one(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
+                   const double* dxt, const msir_params& P, int ug, int up, msir_result* out,
+                   std::vector<msir_step>& hist) {
+  Ctx& c = h->c;
+  int rc;
+  const double k_max = P.k_max > 0 ? P.k_max : 0.1 * n;
+  const int uf = P.uf, u = P.u, ur = P.ur, ux = P.ux;
+  const double uxr = unit_roundoff(ux);
+  const double sqn = sqrt((double)n);
+  const double tau = P.tau > 0 ? P.tau : (ug == P_FP32 ? 1e-6 : 1e-10);
+  double* xa = vbuf(h, h->xa, n);
+  double* xb = vbuf(h, h->xb, n);
+  double* rhat = vbuf(h, h->rhat, n);
+  double* d = vbuf(h, h->d, n);
+  double* th = vbuf(h, h->tmp_hi, n);
+  double* tl = vbuf(h, h->tmp_lo, n);
+  double* t2 = vbuf(h, h->tmp2, n);
+  if (!xa || !xb || !rhat || !d || !th || !tl || !t2) return MSIR_ERR_ALLOC;
+  double* ds = h->dev_small;
+  double* s_dev = ds + 0;
+  double* mon = ds + 32;
+  double* nrm = ds + 40;
+
+  HIP_CHECK(hipEventRecord(h->ev[0], c.stream));
+  rc = norms(c, n, dA, lda, db, nrm);
+  if (rc) return rc;
+  rc = sync_read(h, nrm, 2);
+  if (rc) return rc;
+  const double normA = h->host_small[0], normb = h->host_small[1];
+  rc = do_factor(h, n, dA, lda, uf, P.scaling, P.nb, P.lu_update);
+  if (rc) return rc;
+  float* Au = nullptr;
+  if (up == P_FP32) {
+    Au = (float*)c.grow(h->Au, (size_t)n * n * sizeof(float));
+    if (!Au) return MSIR_ERR_ALLOC;
+    rc = to_fp32(c, n, dA, lda, Au, n);
+    if (rc) return rc;
+  }
+  GmresOp op;
+  op.n = n; op.A = dA; op.lda = lda; op.tmp_hi = th; op.tmp_lo = tl; op.tmp2 = t2; op.mode = 0; op.dinv = nullptr;
+  op.u = ug; op.p = up; op.prec = h->f.prec; op.Au = Au;
+  op.W = h->f.W; op.ldw = n; op.perm = h->f.perm; op.rinv = h->f.rinv;
+  op.R = h->f.scaled ? h->f.R : nullptr; op.S = h->f.scaled ? h->f.S : nullptr;
+  op.mu = h->f.scaled ? h->f.mu : 1.0;
+  op.pinv = h->f.pinv; op.Rp = h->f.scaled ? h->f.Rp : nullptr;
+  op.Xinv = op.Yinv = nullptr;
+  op.inv_prec = -1;
+  if (up != P_DD) {
+    rc = ensure_inverses(h, n, up, &op.Xinv, &op.Yinv);
+    if (rc) return rc;
+    op.inv_prec = up;
+  }
+  HIP_CHECK(hipEventRecord(h->ev[1], c.stream));
+
+  unsigned ev = h->f.scaled ? MSIR_EV_SCALED : 0u;
+  double* x = xa;
+  double* xn = xb;
+  rc = solve_with(h, n, uf, db, nullptr, x, -1, 0);
+  if (rc) return rc;
+  rc = vec_norm_inf(c, n, x, mon);
+  if (rc) return rc;
+  rc = sync_read(h, mon, 2);
+  if (rc) return rc;
+  double xnorm = h->host_small[0];
+  if (h->host_small[1] != 0.0) {
+    HIP_CHECK(hipMemsetAsync(x, 0, n * sizeof(double), c.stream));
+    ev |= MSIR_EV_NAN_X0;
+    xnorm = 0.0;
+  }
+  if (ux != P_FP64) {
+    rc = round_vec(c, n, x, x, ux);
+    if (rc) return rc;
+    rc = vec_norm_inf(c, n, x, mon);
+    if (rc) return rc;
+    rc = sync_read(h, mon, 1);
+    if (rc) return rc;
+    xnorm = h->host_small[0];
+  }
+  auto nbe_of = [&](double s, double xn_) {
+    const double den = normA * xn_ + normb;
+    return den > 0 ? s / den : (s == 0 ? 0.0 : INFINITY);
+  };
+  // convergence test of the modes other than ESTIMATE on iterate xx, whose
+  // double-double residual has inf-norm s_true
+  auto errors_ok = [&](const double* xx, double s_true, double xn_, bool* ok) -> int {
+    *ok = false;
+    if (!isfinite(s_true)) return 0;
+    if (P.conv == MSIR_CONV_BACKWARD) { *ok = nbe_of(s_true, xn_) <= P.tol_nbe; return 0; }
+    if (P.conv == MSIR_CONV_COMPONENTWISE) {
+      double* ce = ds + 58;
+      int r2 = backward_errors(c, n, dA, lda, xx, db, ce);
+      if (r2) return r2;
+      r2 = sync_read(h, ce, 2);
+      if (r2) return r2;
+      *ok = h->host_small[1] <= P.tol_nbe;
+      return 0;
+    }
+    if (P.conv == MSIR_CONV_TRUE) {
+      double* sm = ds + 60;   // holds -1.0
+      double* mm = ds + 52;
+      int r2 = update_into(c, n, xx, th, dxt, sm, P_FP64, mm);
+      if (r2) return r2;
+      r2 = sync_read(h, mm, 4);
+      if (r2) return r2;
+      const double xt = h->host_small[0], df = h->host_small[2];
+      const double fe = xt > 0 ? df / xt : INFINITY;
+      *ok = fe <= unit_roundoff(u) && nbe_of(s_true, xn_) <= unit_roundoff(u);
+    }
+    return 0;
+  };
+  const bool want_true = P.conv != MSIR_CONV_ESTIMATE;
+  bool cged = false, stopped = false;
+  int gm_total = 0;
+  double dprev = INFINITY, rho_max = 0.0;
+  for (int it = 1; it <= P.i_max && !stopped; ++it) {
+    rc = residual(c, n, dA, lda, x, db, ur, ug, rhat, s_dev, want_true);
+    if (rc) return rc;
+    rc = sync_read(h, s_dev, 2);
+    if (rc) return rc;
+    const double s = h->host_small[0], s_true = h->host_small[1];
+    const double nbe_x = isfinite(s) ? nbe_of(s, xnorm) : NAN;
+    if (s == 0.0) { cged = true; stopped = true; break; }
+    if (want_true && isfinite(s)) {
+      bool ok;
+      rc = errors_ok(x, s_true, xnorm, &ok);
+      if (rc) return rc;
+      if (ok) { cged = true; stopped = true; break; }
+    }
+    int k = -1;
+    rc = gmres(c, h->gw, op, rhat, tau, k_max, P.restart, d, &k);
+    if (rc) return rc;
+    gm_total += k;
+    rc = update_into(c, n, x, xn, d, s_dev, ux, mon);
+    if (rc) return rc;
+    rc = sync_read(h, mon, 4);
+    if (rc) return rc;
+    const double md = h->host_small[0], mx = h->host_small[1], mxn = h->host_small[2];
+    const bool bad = h->host_small[3] != 0.0;
+    msir_step st;
+    memset(&st, 0, sizeof(st));
+    st.level = 0; st.uf = uf; st.u = u; st.ur = ur; st.stage = 2; st.iter = it; st.k_gmres = k;
+    st.counted = 1; st.rnorm = s; st.nbe = nbe_x; st.rho_max = rho_max;
+    if (bad) {
+      st.z = st.v = st.phi = NAN;
+      st.events = ev | MSIR_EV_NAN_D;
+      hist.push_back(st);
+      stopped = true;
+      break;
+    }
+    const double delta = s * md;
+    const double z = mx > 0 ? delta / mx : (delta == 0 ? 0.0 : INFINITY);
+    const double v = isinf(dprev) ? 0.0 : delta / dprev;
+    rho_max = std::max(rho_max, v);
+    const double phi = rho_max < 1.0 ? z / (1.0 - rho_max) : INFINITY;
+    dprev = delta;
+    std::swap(x, xn);
+    xnorm = mxn;
+    st.z = z; st.v = v; st.rho_max = rho_max; st.phi = phi; st.events = ev;
+    ev = 0;
+    if (P.conv == MSIR_CONV_ESTIMATE && 0.0 <= phi && phi <= sqn * uxr) {
+      st.events |= MSIR_EV_CONVERGED;
+      hist.push_back(st);
+      cged = true;
+      stopped = true;
+      break;
+    }
+    hist.push_back(st);
+  }
+  if (!stopped && want_true) {
+    // i_max steps done: the last iterate may still pass the test
+    rc = residual(c, n, dA, lda, x, db, ur, ug, rhat, s_dev, true);
+    if (rc) return rc;
+    rc = sync_read(h, s_dev, 2);
+    if (rc) return rc;
+    bool ok;
+    rc = errors_ok(x, h->host_small[1], xnorm, &ok);
+    if (rc) return rc;
+    cged = ok;
+  }
+  const int status = cged ? MSIR_OK : MSIR_NOT_CONVERGED;
+  HIP_CHECK(hipEventRecord(h->ev[2], c.stream));
+  HIP_CHECK(hipMemcpyAsync(dx, x, n * sizeof(double), hipMemcpyDeviceToDevice, c.stream));
+  if (out) {
+    memset(out, 0, sizeof(*out));
+    double* eo = ds + 56;
+    rc = vec_norm_inf(c, n, x, eo);
+    if (rc) return rc;
+    rc = backward_errors(c, n, dA, lda, x, db, eo + 2);
+    if (rc) return rc;
+    rc = sync_read(h, eo, 4);
+    if (rc) return rc;
+    const double xf = h->host_small[0], rmax = h->host_small[2], cbe = h->host_small[3];
+    const double den = normA * xf + normb;
+    out->nbe = den > 0 ? rmax / den : (rmax > 0 ? INFINITY : 0.0);
+    out->cbe = cbe;
+    out->ferr = NAN;
+    if (dxt) {
+      double* sm = ds + 60;
+      double* mm = ds + 52;
+      rc = update_into(c, n, x, th, dxt, sm, P_FP64, mm);
+      if (rc) return rc;
+      rc = sync_read(h, mm, 4);
+      if (rc) return rc;
+      const double xt = h->host_small[0], df = h->host_small[2];
+      out->ferr = xt > 0 ? df / xt : INFINITY;
+    }
+    out->cged = cged ? 1 : 0;
+    out->status = status;
+    out->steps = (int)hist.size();
+    out->n_lu = 1;
+    out->gmres_iters = gm_total;
+    out->final_uf = uf; out->final_u = u; out->final_ur = ur;
+    HIP_CHECK(hipEventSynchronize(h->ev[2]));
+    float ms_all = 0.0f, ms_f = 0.0f;
+    (void)hipEventElapsedTime(&ms_f, h->ev[0], h->ev[1]);
+    (void)hipEventElapsedTime(&ms_all, h->ev[0], h->ev[2]);
+    out->t_factor_ms = ms_f;
+    out->t_refine_ms = ms_all - ms_f;
+  }
+  HIP_CHECK(hipStreamSynchronize(c.stream));
+  return status;
+}
+
+int msir_gmres_ir5(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
+                   const double* dxt, const msir_params* params, msir_prec ug, msir_prec up, msir_result* out,
+                   msir_step* hist, int hist_cap, int* hist_len) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (!dA) return -3;
+  if (lda < n) return -4;
+  if (!db) return -5;
+  if (!dx) return -6;
+  msir_params P;
+  if (params) P = *params; else msir_params_default(&P);
+  if (P.uf < MSIR_FP16 || P.uf > MSIR_FP64) return -8;
+  if (P.u != MSIR_FP32 && P.u != MSIR_FP64) return -8;
+  if (P.ur != MSIR_FP64 && P.ur != MSIR_DD) return -8;
+  if (P.ux != MSIR_FP64 && P.ux != P.u) return -8;
+  if (P.i_max < 1 || P.restart < 0) return -8;
+  if (P.conv < MSIR_CONV_ESTIMATE || P.conv > MSIR_CONV_COMPONENTWISE) return -8;
+  if (P.conv == MSIR_CONV_TRUE && !dxt) return -7;
+  if (P.nb != 0 && !nb_ok(n, P.uf, P.nb)) return -8;
+  if (P.lu_update != MSIR_LU_MFMA && P.lu_update != MSIR_LU_FMA) return -8;
+  // u_g in {FP32, FP64} not more precise than u; u_p in {FP32, FP64, DD}
+  if ((ug != MSIR_FP32 && ug != MSIR_FP64) || unit_roundoff(ug) < unit_roundoff(P.u)) return -9;
+  if (up != MSIR_FP32 && up != MSIR_FP64 && up != MSIR_DD) return -9;
+  if (hist_cap < 0) return -11;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  std::vector<msir_step> H;
+  int rc = ir5_one(h, n, dA, lda, db, dx, dxt, P, ug, up, out, H);
+  unsigned terr = 0;
+  if (rc >= 0 && trsv_check(h->c, &terr) == 0 && terr) {
+    msir_set_error("substitution wait expired", __FILE__, __LINE__);
+    rc = MSIR_ERR_TIMEOUT;
+  }
+  if (hist_len) *hist_len = (int)H.size();
+  if (hist && hist_cap > 0) memcpy(hist, H.data(), std::min((size_t)hist_cap, H.size()) * sizeof(msir_step));
+  return rc;
+}
+
 int msir_timing(msir_handle* h, int enable) {
   if (!h) return -1;
   Ctx& c = h->c;

@@ -191,3 +191,34 @@ def test_componentwise_convergence(M, h, cfg, n, tol):
     assert_same_history(hist, ref)
     assert rc == 0 and res.cged == 1
     assert res.cbe <= tol and OMET.cbe(A, xg, b) <= tol
+
+
+IR5_COMBOS = [("fp16", "fp32", "fp64", "fp32", "fp32"), ("fp16", "fp32", "fp64", "fp32", "fp64"),
+              ("fp16", "fp64", "dd", "fp32", "fp64"), ("fp32", "fp64", "dd", "fp32", "dd"),
+              ("fp16", "fp64", "dd", "fp64", "fp64")]
+
+
+@pytest.mark.parametrize("combo", IR5_COMBOS)
+@pytest.mark.parametrize("n,kappa,mode", [(100, 1e3, 3), (256, 3e4, 2)])
+def test_gmres_ir5_vs_oracle(M, h, combo, n, kappa, mode):
+    # GMRES-IR5 (u_f, u, u_r, u_g, u_p): same step count and GMRES counts (+-1) as the
+    # oracle, converged to nbe <= 1e-15, x within the solve tests' tolerance
+    uf, u, ur, ug, up = combo
+    A, x, b = WL.randsvd(n, kappa, mode, WL.rng_for(43, n))
+    prm = dict(uf=uf, u=u, ur=ur, k_max=40, i_max=10)
+    At = M.colmajor(torch.from_numpy(np.asfortranarray(A)).to(DEV))
+    bt = torch.from_numpy(b).to(DEV)
+    xt = torch.from_numpy(x).to(DEV)
+    xg, res, hist, rc = M.gmres_ir5(h, At, bt, ug, up, x_true=xt, P=M.params(lu_update="fma", **prm))
+    ref = OM.gmres_ir5(A, b, OM.Params(**prm), ug=ug, up=up, x_true=x)
+    kg, ko = [s.k_gmres for s in hist], [s.k for s in ref.history]
+    print(combo, "gpu", kg, "nbe %.2e" % res.nbe, "| oracle", ko, "nbe %.2e" % ref.nbe)
+    assert all(s.stage == 2 and s.level == 0 for s in hist)
+    assert abs(len(kg) - len(ko)) <= 1
+    for a, c in zip(kg, ko):
+        assert abs(a - c) <= 1
+    assert rc == 0 and res.cged == 1 and ref.cged
+    assert res.nbe <= 1e-15
+    kinf = WL.kappa_inf(A)
+    tol = max(1e-12 * max(1.0, kappa * 1e-4), 4 * kinf * (res.nbe + ref.nbe))
+    assert np.abs(xg.cpu().numpy() - ref.x).max() <= tol * np.abs(ref.x).max()

@@ -231,3 +231,24 @@ def test_componentwise_stops_at_first_iterate_meeting_tolerance():
     assert not prev.cged and metrics.cbe(A, prev.x, b) > tol
     loose = M.msir(A, b, M.Params(conv="componentwise", tol_nbe=1e-13), x_true=x)
     assert loose.cged and len(loose.history) <= K
+
+
+def test_gmres_ir5_near_identity_operator_one_iteration_per_step():
+    # u_f = u_g = u_p = fp64: M^{-1} A = I + E with ||E|| ~ kappa u_64 << tau, so every
+    # GMRES call stops after one iteration; an unreachable tolerance runs i_max steps
+    A, x, b = WL.randsvd(120, 1e2, 3, WL.rng_for(42, 0))
+    r = M.gmres_ir5(A, b, M.Params(uf="fp64", u="fp64", ur="dd", tol_nbe=1e-30, i_max=3), ug="fp64", up="fp64",
+                    x_true=x)
+    assert [st.k for st in r.history] == [1, 1, 1]
+    assert not r.cged and r.status == 1
+    assert all(st.stage == M.GMRES and st.level == 0 for st in r.history)
+    assert metrics.nbe(A, r.x, b) <= 1e-15
+
+
+def test_gmres_ir5_stops_at_i_max_and_on_convergence():
+    A, x, b = WL.randsvd(100, 1e3, 3, WL.rng_for(43, 100))
+    r = M.gmres_ir5(A, b, M.Params(uf="fp16", u="fp32", ur="fp64", k_max=40, i_max=1, tol_nbe=1e-30), ug="fp32",
+                    up="fp32")
+    assert len(r.history) == 1 and not r.cged
+    r = M.gmres_ir5(A, b, M.Params(uf="fp16", u="fp32", ur="fp64", k_max=40), ug="fp32", up="fp64")
+    assert r.cged and metrics.nbe(A, r.x, b) <= 1e-15 and 0 < len(r.history) < 10
