@@ -255,30 +255,34 @@ __device__ __forceinline__ double sum16_lanes(const double* p) { return sum_lane
 // Ordered folds of strided partial sums p[s * stride] for s in [s_lo, s_hi): the
 // loads are issued sixteen at a time, the additions stay in slice order.
 __device__ __forceinline__ double fold_sum(const double* __restrict__ p, size_t stride, int s_lo, int s_hi) {
+  // every batch (the last one partly masked) has all its loads in flight before the
+  // first addition, so a fold costs one memory round trip per 16 slices
   double t = 0.0;
-  int s = s_lo;
-  for (; s + 16 <= s_hi; s += 16) {
+  for (int s = s_lo; s < s_hi; s += 16) {
     double q[16];
 #pragma unroll
-    for (int k = 0; k < 16; ++k) q[k] = p[(size_t)(s + k) * stride];
+    for (int k = 0; k < 16; ++k) q[k] = (s + k < s_hi) ? p[(size_t)(s + k) * stride] : 0.0;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) t = __dadd_rn(t, q[k]);
+    for (int k = 0; k < 16; ++k)
+      if (s + k < s_hi) t = __dadd_rn(t, q[k]);
   }
-  for (; s < s_hi; ++s) t = __dadd_rn(t, p[(size_t)s * stride]);
   return t;
 }
 // (h, l) += sum of sign * (ph[s], pl[s]) in double-double, slice order
 __device__ __forceinline__ void fold_dd(const double* __restrict__ ph, const double* __restrict__ pl, size_t stride,
                                         int s_lo, int s_hi, double sign, double& h, double& l) {
-  int s = s_lo;
-  for (; s + 8 <= s_hi; s += 8) {
+  for (int s = s_lo; s < s_hi; s += 8) {
     double qh[8], ql[8];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) { qh[k] = ph[(size_t)(s + k) * stride]; ql[k] = pl[(size_t)(s + k) * stride]; }
+    for (int k = 0; k < 8; ++k) {
+      const bool in = s + k < s_hi;
+      qh[k] = in ? ph[(size_t)(s + k) * stride] : 0.0;
+      ql[k] = in ? pl[(size_t)(s + k) * stride] : 0.0;
+    }
 #pragma unroll
-    for (int k = 0; k < 8; ++k) dd_add(h, l, sign * qh[k], sign * ql[k], h, l);
+    for (int k = 0; k < 8; ++k)
+      if (s + k < s_hi) dd_add(h, l, sign * qh[k], sign * ql[k], h, l);
   }
-  for (; s < s_hi; ++s) dd_add(h, l, sign * ph[(size_t)s * stride], sign * pl[(size_t)s * stride], h, l);
 }
 
 // Block-wide sum of a double over blockDim.x threads (multiple of 64), deterministic order.
