@@ -372,6 +372,106 @@ __global__ __launch_bounds__(SNT) void k_swap_trsm(typename Store<P>::T* __restr
     if (k < jb) w[j0 + k] = from_a<P>(u[k]);
 }
 
+// Panels up to 32 wide: the same interchanges and U12, with the block rows j0..j0+jb
+// of each column moved as one contiguous vector (two to four 16-byte accesses) and
+// the interchange done in LDS, so that memory is touched scattered only for the
+// rows outside the block that take part in the interchange (at most jb of them).
+// An outside row only ever receives a row of the block (the block positions hold
+// rows of the block until their own pivot step), so its new value is an original
+// block value.
+template <int P, int KMAX>
+__global__ __launch_bounds__(SNT) void k_swap_trsm_v(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0,
+                                                     int jb, const int* __restrict__ moved) {
+  typedef typename Arith<P>::T AT;
+  typedef typename Store<P>::T ST;
+  static_assert(KMAX <= 32 && (KMAX * sizeof(ST)) % 16 == 0, "whole 16-byte vectors");
+  constexpr int MM = 2 * KMAX;
+  constexpr int NV = KMAX * (int)sizeof(ST) / 16;
+  const int tid = threadIdx.x;
+  const int jr = j0 + jb;
+  __shared__ int s_src[KMAX];                  // source row of block row k
+  __shared__ int s_odst[KMAX], s_osrc[KMAX];   // outside destinations, their block sources
+  __shared__ int s_cnt, s_nout;
+  __shared__ AT sL[KMAX][KMAX + 1];
+  __shared__ AT sb[KMAX][SNT];                 // this workgroup's block rows, one column per lane
+  if (tid == 0) { s_cnt = moved[0]; s_nout = 0; }
+  for (int k = tid; k < KMAX; k += SNT) s_src[k] = j0 + k;
+  for (int e = tid; e < KMAX * KMAX; e += SNT) {
+    const int i = e % KMAX, k = e / KMAX;
+    sL[i][k] = (i < jb && k < jb) ? to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + i], AT(0)) : AT(0);
+  }
+  __syncthreads();
+  const int cnt = min(s_cnt, MM);
+  for (int i = tid; i < cnt; i += SNT) {
+    const int d = moved[1 + 2 * i], sr = moved[2 + 2 * i];
+    if (d >= j0 && d < jr) {
+      s_src[d - j0] = sr;
+    } else {
+      const int q = atomicAdd(&s_nout, 1);
+      if (q < KMAX) { s_odst[q] = d; s_osrc[q] = sr; }
+    }
+  }
+  __syncthreads();
+  const int nout = min(s_nout, KMAX);
+  int col = blockIdx.x * SNT + tid;
+  if (col >= j0) col += jb;
+  if (col >= n) return;
+  ST* w = W + (size_t)col * ldw;
+  const bool right = col >= jr;
+  const bool vec = jb == KMAX && ((uintptr_t)(w + j0) % 16) == 0;
+  // 1. the block rows (original values) and the outside sources, all in flight
+  ST blk[KMAX], ext[KMAX];
+  if (vec) {
+    uint4 raw[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) raw[v] = reinterpret_cast<const uint4*>(w + j0)[v];
+    __builtin_memcpy(blk, raw, sizeof(blk));
+  } else {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) blk[k] = (k < jb) ? w[j0 + k] : ST(0);
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int sr = s_src[k];
+    ext[k] = (k < jb && sr >= jr) ? w[sr] : ST(0);
+  }
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) sb[k][tid] = to_a<P>(blk[k], AT(0));
+  // 2. outside destinations receive original block values
+  for (int q = 0; q < nout; ++q) w[s_odst[q]] = from_a<P>(sb[s_osrc[q] - j0][tid]);
+  // 3. the interchanged block rows; right of the panel, U12 = L11^{-1} A12
+  AT u[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    const int sr = s_src[k];
+    u[k] = (k >= jb) ? AT(0) : (sr >= jr ? to_a<P>(ext[k], AT(0)) : sb[sr - j0][tid]);
+  }
+  if (right) {
+#pragma unroll
+    for (int k = 1; k < KMAX; ++k) {
+      if (k < jb) {
+        AT acc = u[k];
+#pragma unroll
+        for (int i = 0; i < KMAX; ++i)
+          if (i < k) acc = a_fma(-sL[k][i], u[i], acc);
+        u[k] = acc;
+      }
+    }
+  }
+  if (vec) {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) blk[k] = from_a<P>(u[k]);
+    uint4 raw[NV];
+    __builtin_memcpy(raw, blk, sizeof(blk));
+#pragma unroll
+    for (int v = 0; v < NV; ++v) reinterpret_cast<uint4*>(w + j0)[v] = raw[v];
+  } else {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < jb) w[j0 + k] = from_a<P>(u[k]);
+  }
+}
+
 // ------------------------------------------------------------------ trailing update
 // A22 <- fl_f(A22 - L21 U12), 64x64 output tile per workgroup (4 waves, 2x2
 // 32x32 MFMA tiles for fp16/bf16 and fp32 factors; 4x4 register micro-tiles with
@@ -585,9 +685,14 @@ static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info, bool 
     const int jb = (n - j0 < NB) ? n - j0 : NB;
     MSIR_TIMED(c, 0, (panel_dispatch<P, NB>(c, W, ldw, n, j0, jb, ipiv, info, moved)));
     const int others = n - jb;
-    if (others > 0)
-      MSIR_TIMED(c, 1, (k_swap_trsm<P, NB><<<(others + SNT - 1) / SNT, SNT, 0, c.stream>>>(
-                           (typename Store<P>::T*)W, ldw, n, j0, jb, moved)));
+    if (others > 0) {
+      if constexpr (NB <= 32 && (NB * sizeof(typename Store<P>::T)) % 16 == 0)
+        MSIR_TIMED(c, 1, (k_swap_trsm_v<P, NB><<<(others + SNT - 1) / SNT, SNT, 0, c.stream>>>(
+                             (typename Store<P>::T*)W, ldw, n, j0, jb, moved)));
+      else
+        MSIR_TIMED(c, 1, (k_swap_trsm<P, NB><<<(others + SNT - 1) / SNT, SNT, 0, c.stream>>>(
+                             (typename Store<P>::T*)W, ldw, n, j0, jb, moved)));
+    }
     const int mt = n - j0 - jb;
     if (mt > 0) {
       dim3 g((mt + GT - 1) / GT, (mt + GT - 1) / GT);
