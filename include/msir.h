@@ -283,7 +283,7 @@ typedef enum {
     MSIR_T_RESID = 5,    /* residual b - A x and its scaling                     */
     MSIR_T_ARNOLDI = 6,  /* modified Gram-Schmidt + Givens                       */
     MSIR_T_TRGEMV = 7,   /* one triangular product with an fp32 inverse factor   */
-    MSIR_T_OTHER = 8,
+    MSIR_T_FOLD = 8,     /* fold of a product's slice partial sums into its output */
     MSIR_T_MATVEC64 = 9, /* A v inside GMRES with the float64 A (fp64 or dd)      */
     MSIR_T_TRGEMV64 = 10,/* one triangular product with an fp64 inverse factor   */
     MSIR_T_COUNT = 11

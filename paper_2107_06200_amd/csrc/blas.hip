@@ -260,11 +260,14 @@ int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, c
   double* ph = c.ws_part_hi(g.ns * (size_t)n);
   double* pl = c.ws_part_lo(g.ns * (size_t)n);
   if (!ph || !pl) return MSIR_ERR_ALLOC;
-  const int _slot = c.tbegin(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
+  int _slot = c.tbegin_kernel(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
   int rc;
   if (p == P_FP32) rc = gemv_partials(c, g, n, P_FP32, Au, ldau, v, nullptr, nullptr, 0, ph, pl, nullptr, skip);
   else rc = gemv_partials(c, g, n, P_FP64, A, lda, v, nullptr, nullptr, p == P_DD ? 1 : 0, ph, pl, nullptr, skip);
-  if (!rc) rc = gemv_finish(c, g, n, ph, pl, 1.0, nullptr, p, y_hi, y_lo, skip, operm, oR);
+  c.tend_kernel(_slot);
+  if (rc) return rc;
+  _slot = c.tbegin(MSIR_T_FOLD);
+  rc = gemv_finish(c, g, n, ph, pl, 1.0, nullptr, p, y_hi, y_lo, skip, operm, oR);
   c.tend(_slot);
   return rc;
 }

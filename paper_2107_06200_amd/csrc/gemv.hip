@@ -24,6 +24,8 @@
 // double-double with exact products (u_r = quadruple-precision stand-in);
 // MODE 2 does both in one pass (the float64 residual of the method plus an
 // almost exactly rounded one for the convergence test).
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "msir_internal.hpp"
 
@@ -378,8 +380,16 @@ static void launch_one(Ctx& c, int grid_x, int grid_y, int n, const TA* A, int l
   constexpr bool F32 = sizeof(TA) == 4;
   constexpr int WV = gemv_waves(F32, MODE, TRI);
   constexpr bool DB = gemv_dbuf(F32, MODE, TRI);
-  k_gemv<TA, MODE, TRI, WV, DB><<<dim3(grid_x, grid_y), 64 * WV, 0, c.stream>>>(n, A, lda, aligned, in, chunk, ph, pl,
-                                                                              px, skip);
+  if (c.ext_slot >= 0) {
+    // timing: the events are part of this dispatch (kernel start and end)
+    const int sl = c.ext_slot;
+    c.ext_slot = -1;
+    hipExtLaunchKernelGGL(k_gemv<TA, MODE, TRI, WV, DB>, dim3(grid_x, grid_y), dim3(64 * WV), 0, c.stream,
+                          c.ev_pool[sl], c.ev_pool[sl + 1], 0, n, A, lda, aligned, in, chunk, ph, pl, px, skip);
+  } else {
+    k_gemv<TA, MODE, TRI, WV, DB><<<dim3(grid_x, grid_y), 64 * WV, 0, c.stream>>>(n, A, lda, aligned, in, chunk, ph,
+                                                                                pl, px, skip);
+  }
 }
 
 template <typename TA, int MODE>

@@ -267,9 +267,12 @@ int trgemv(Ctx& c, int n, int store_prec, const void* T, int tri, const double* 
   const GemvPlan g = gemv_plan(n, tri);
   double* part = (double*)c.grow(c.tr_part, (size_t)g.ns * n * sizeof(double));
   if (!part) return MSIR_ERR_ALLOC;
-  const int slot = c.tbegin(store_prec == P_FP32 ? MSIR_T_TRGEMV : MSIR_T_TRGEMV64);
+  int slot = c.tbegin_kernel(store_prec == P_FP32 ? MSIR_T_TRGEMV : MSIR_T_TRGEMV64);
   int rc = gemv_partials(c, g, n, store_prec, T, n, x, perm, R, 0, part, nullptr, nullptr, skip);
-  if (!rc) rc = gemv_finish(c, g, n, part, nullptr, mu, S, p, y, nullptr, skip);
+  c.tend_kernel(slot);
+  if (rc) return rc;
+  slot = c.tbegin(MSIR_T_FOLD);
+  rc = gemv_finish(c, g, n, part, nullptr, mu, S, p, y, nullptr, skip);
   c.tend(slot);
   return rc;
 }
@@ -292,27 +295,30 @@ int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au
     GemvIn in;
     in.x = v;
     in.prow = pinv;
-    const int slot = c.tbegin(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
+    const int slot = c.tbegin_kernel(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
     if (p == P_FP32) rc = gemv_partials(c, gm, n, P_FP32, Au, n, in, 0, pa, nullptr, nullptr, skip);
     else rc = gemv_partials(c, gm, n, P_FP64, A, lda, in, 0, pa, nullptr, nullptr, skip);
-    c.tend(slot);
+    c.tend_kernel(slot);
     if (rc) return rc;
   }
   const int cls = inv_prec == P_FP32 ? MSIR_T_TRGEMV : MSIR_T_TRGEMV64;
   {
     GemvIn in;
     in.xpart = pa; in.xns = gm.ns; in.xchunk = gm.chunk; in.xtri = 0; in.xround = p; in.xscale = Rp;
-    const int slot = c.tbegin(cls);
+    const int slot = c.tbegin_kernel(cls);
     rc = gemv_partials(c, gl, n, inv_prec, X, n, in, 0, pb, nullptr, nullptr, skip);
-    c.tend(slot);
+    c.tend_kernel(slot);
     if (rc) return rc;
   }
   {
     GemvIn in;
     in.xpart = pb; in.xns = gl.ns; in.xchunk = gl.chunk; in.xtri = 1; in.xround = p;
-    const int slot = c.tbegin(cls);
+    int slot = c.tbegin_kernel(cls);
     rc = gemv_partials(c, gu, n, inv_prec, Y, n, in, 0, pa, nullptr, nullptr, skip);
-    if (!rc) rc = gemv_finish(c, gu, n, pa, nullptr, mu, S, u, out, nullptr, skip);
+    c.tend_kernel(slot);
+    if (rc) return rc;
+    slot = c.tbegin(MSIR_T_FOLD);
+    rc = gemv_finish(c, gu, n, pa, nullptr, mu, S, u, out, nullptr, skip);
     c.tend(slot);
   }
   return rc;

@@ -64,6 +64,26 @@ void Ctx::tend(int slot) {
   (void)hipEventRecord(ev_pool[slot + 1], stream);
 }
 
+int Ctx::tbegin_kernel(int cls) {
+  if (!timing) return -1;
+  if (ev_used + 2 > ev_cap) tflush();
+  if (ev_used + 2 > ev_cap) return -1;
+  const int slot = ev_used;
+  ev_used += 2;
+  ev_cls[slot] = cls;
+  ext_slot = slot;
+  return slot;
+}
+
+void Ctx::tend_kernel(int slot) {
+  if (slot < 0) return;
+  if (ext_slot == slot) {   // no launch took the events: record an empty interval
+    ext_slot = -1;
+    (void)hipEventRecord(ev_pool[slot], stream);
+    (void)hipEventRecord(ev_pool[slot + 1], stream);
+  }
+}
+
 void Ctx::tflush() {
   if (ev_used == 0) return;
   (void)hipStreamSynchronize(stream);

@@ -52,6 +52,12 @@ struct Ctx {
   int tbegin(int cls);           // returns a slot or -1
   void tend(int slot);
   void tflush();                 // fold recorded events into the totals
+  // Kernel-attached timing: the next streaming-product launch carries the slot's
+  // events in its dispatch (start and end of the kernel itself, no separate event
+  // packets); tend_kernel records them only if no launch took the slot.
+  int ext_slot = -1;
+  int tbegin_kernel(int cls);
+  void tend_kernel(int slot);
 };
 
 // Bracket a launch with timing events when enabled.

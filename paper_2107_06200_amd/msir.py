@@ -88,7 +88,7 @@ _SIG = {
     "msir_timing_get": (_I, [_P, _I, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(_D)]),
 }
 
-TIMERS = ["panel", "swap", "gemm", "trsv", "matvec32", "resid", "arnoldi", "trgemv32", "other", "matvec64",
+TIMERS = ["panel", "swap", "gemm", "trsv", "matvec32", "resid", "arnoldi", "trgemv32", "fold", "matvec64",
           "trgemv64"]
 
 
