@@ -256,7 +256,7 @@ int residual(Ctx& c, int n, const double* A, int lda, const double* x, const dou
 // y = A v with p in {FP32 (Au = fp32 copy of A), FP64, DD}; v holds values in u (float64 array).
 int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
            double* y_hi, double* y_lo, const int* skip, const int* operm, const double* oR) {
-  const GemvPlan g = gemv_plan(n, 0);
+  const GemvPlan g = gemv_plan(n, 0, p == P_FP32 ? P_FP32 : P_FP64, p == P_DD ? 1 : 0);
   double* ph = c.ws_part_hi(g.ns * (size_t)n);
   double* pl = c.ws_part_lo(g.ns * (size_t)n);
   if (!ph || !pl) return MSIR_ERR_ALLOC;

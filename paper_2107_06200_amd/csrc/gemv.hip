@@ -332,35 +332,49 @@ __global__ __launch_bounds__(256) void k_gemv_finish(int n, int ns, int chunk, c
   }
 }
 
-GemvPlan gemv_plan(int n, int tri) {
+// Columns one batch of a workgroup covers (columns in flight per lane x waves).
+static int gemv_step(bool fp32, int mode, int tri);
+static constexpr int gemv_waves(bool fp32, int mode, int tri);
+
+GemvPlan gemv_plan(int n, int tri, int a_prec, int mode) {
   GemvPlan g;
   g.tri = tri;
   g.rb = (n + GV_ROWS - 1) / GV_ROWS;
-  // columns the row blocks need in total; slice width so that ~GV_TARGET (row block,
-  // slice) pairs are busy, at least 4 columns per wave and at most the LDS bound
+  // columns the row blocks need in total; the slice width is a whole number of the
+  // kernel's batches, at least what spreads the columns over GV_TARGET workgroups, and
+  // widened until the busy (row block, slice) pairs fit GV_TARGET, so that no compute
+  // unit carries two full slices (the last of them would set the launch's end)
   long long cols = 0;
   for (int r = 0; r < g.rb; ++r) {
     const int rlo = r * GV_ROWS, rhi = n < rlo + GV_ROWS ? n : rlo + GV_ROWS;
     cols += tri == 0 ? n : (tri == 1 ? rhi : n - rlo);
   }
-  // slices are whole batches (GV_BATCH columns: eight per wave), so no batch is
-  // partly empty except at the matrix edge
+  const int step = gemv_step(a_prec == P_FP32, mode, tri);
+  // triangular products (the ones that stage their input by folding a producer's
+  // partial sums, GemvIn::xpart) take at most one slice element per thread
+  const int nt = 64 * gemv_waves(a_prec == P_FP32, mode, tri);
+  const int cap = (tri != 0 && nt < GV_MAXCHUNK) ? nt : GV_MAXCHUNK;
+  auto pairs_for = [&](int chunk) {
+    const int ns = (n + chunk - 1) / chunk;
+    int nwg = 0;
+    for (int r = 0; r < g.rb; ++r) {
+      const int rlo = r * GV_ROWS, rhi = n < rlo + GV_ROWS ? n : rlo + GV_ROWS;
+      const int s_lo = tri == 2 ? rlo / chunk : 0;
+      const int s_hi = tri == 1 ? (rhi + chunk - 1) / chunk : ns;
+      nwg += s_hi - s_lo;
+    }
+    return nwg;
+  };
   long long chunk = (cols + GV_TARGET - 1) / GV_TARGET;
-  chunk = (chunk + GV_BATCH / 2) / GV_BATCH * GV_BATCH;
-  if (chunk < GV_BATCH) chunk = GV_BATCH;
-  if (chunk > GV_MAXCHUNK) chunk = GV_MAXCHUNK;
+  chunk = (chunk + step - 1) / step * step;
+  if (chunk < step) chunk = step;
+  if (chunk > cap) chunk = cap;
   if (n > 0 && chunk > n) chunk = n;
   if (chunk < 1) chunk = 1;
+  while (n > 0 && chunk + step <= cap && chunk < n && pairs_for((int)chunk) > GV_TARGET) chunk += step;
   g.chunk = (int)chunk;
   g.ns = n > 0 ? (int)((n + chunk - 1) / chunk) : 1;
-  // busy (row block, slice) pairs: the compact grid of a triangular product
-  g.nwg = 0;
-  for (int r = 0; r < g.rb; ++r) {
-    const int rlo = r * GV_ROWS, rhi = n < rlo + GV_ROWS ? n : rlo + GV_ROWS;
-    const int s_lo = tri == 2 ? rlo / g.chunk : 0;
-    const int s_hi = tri == 1 ? (rhi + g.chunk - 1) / g.chunk : g.ns;
-    g.nwg += s_hi - s_lo;
-  }
+  g.nwg = n > 0 ? pairs_for(g.chunk) : 0;
   return g;
 }
 
@@ -373,6 +387,10 @@ static constexpr int gemv_waves(bool fp32, int mode, int tri) {
   return mode != 0 ? 16 : (fp32 && tri == 0 ? 16 : 8);
 }
 static constexpr bool gemv_dbuf(bool fp32, int mode, int tri) { return fp32 && mode == 0 && tri != 0; }
+static int gemv_step(bool fp32, int mode, int tri) {
+  const int unr = (fp32 || (mode == 0 && tri == 0)) ? 8 : 4;   // UNR of k_gemv
+  return unr * gemv_waves(fp32, mode, tri);
+}
 
 template <typename TA, int MODE, int TRI>
 static void launch_one(Ctx& c, int grid_x, int grid_y, int n, const TA* A, int lda, bool aligned, const GemvIn& in,

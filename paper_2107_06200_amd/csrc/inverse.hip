@@ -264,7 +264,7 @@ int square_to_f32(Ctx& c, int n, const double* X, float* Xf) {
 int trgemv(Ctx& c, int n, int store_prec, const void* T, int tri, const double* x, const int* perm, const double* R,
            double mu, const double* S, int p, double* y, const int* skip) {
   if (tri != 1 && tri != 2) return -3;
-  const GemvPlan g = gemv_plan(n, tri);
+  const GemvPlan g = gemv_plan(n, tri, store_prec);
   double* part = (double*)c.grow(c.tr_part, (size_t)g.ns * n * sizeof(double));
   if (!part) return MSIR_ERR_ALLOC;
   int slot = c.tbegin_kernel(store_prec == P_FP32 ? MSIR_T_TRGEMV : MSIR_T_TRGEMV64);
@@ -286,7 +286,7 @@ int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au
                  const double* Rp, int inv_prec, const void* X, const void* Y, double mu, const double* S, int u,
                  double* out, const int* skip) {
   if (p != P_FP32 && p != P_FP64) return -3;
-  const GemvPlan gm = gemv_plan(n, 0), gl = gemv_plan(n, 1), gu = gemv_plan(n, 2);
+  const GemvPlan gm = gemv_plan(n, 0, p), gl = gemv_plan(n, 1, inv_prec), gu = gemv_plan(n, 2, inv_prec);
   double* pa = c.ws_part_hi((size_t)(gm.ns > gu.ns ? gm.ns : gu.ns) * n);
   double* pb = (double*)c.grow(c.tr_part, (size_t)gl.ns * n * sizeof(double));
   if (!pa || !pb) return MSIR_ERR_ALLOC;

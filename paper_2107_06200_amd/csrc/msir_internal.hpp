@@ -139,7 +139,9 @@ struct GemvPlan {
   int chunk = 1;   // columns per slice
   int nwg = 0;     // triangular: (row block, slice) pairs that meet the triangle
 };
-GemvPlan gemv_plan(int n, int tri);
+// Launch plan of a product with an n x n operand (tri 0 full, 1 lower, 2 upper) of
+// storage a_prec accumulated in mode (see gemv_partials).
+GemvPlan gemv_plan(int n, int tri, int a_prec = P_FP64, int mode = 0);
 // Input of a streaming product: a plain vector x (optionally gathered, xin_j = R[perm[j]]
 // x[perm[j]]), or the partial sums of the producing product (xpart[s * n + j] over that
 // product's slices; its plan's ns, chunk and tri select the slices of element j), folded
