@@ -41,6 +41,9 @@ def parse():
                     help="trailing update of the fp16/bf16 LU: matrix cores or fp32 FMA chains")
     ap.add_argument("--copy-only", type=int, default=0, metavar="MB",
                     help="only copy MB megabytes device to device once (calibrates HBM byte counters)")
+    ap.add_argument("--sparse", action="store_true",
+                    help="time the CSR solve on the synthetic sparse workload instead (n=4096, 16 nonzeros "
+                         "per row, magnitude spread 300; the multistage workload's solver parameters)")
     return ap.parse_args()
 
 
@@ -152,10 +155,53 @@ def cpu_baseline(A, b, hs):
                           t_total))}
 
 
+def sparse_bench(args):
+    """Solves/s of Alg. 4 with a sparse A in CSR form (residual and GMRES A v on the CSR
+    arrays); inputs resident in HBM before the timed region."""
+    import numpy as np
+    import torch
+    from paper_2107_06200_amd import msir as M
+    from paper_2107_06200_amd import workloads as WL
+    n = args.n or 4096
+    per_row, scale = 16, 300.0
+    rp, ci, v, A, x_true, b = WL.sparse_system(n, per_row, scale, WL.rng_for(61, n))
+    dev = torch.device("cuda:0")
+    M.lib()
+    h = M.Handle(0)
+    t_rp, t_ci, t_v = (torch.from_numpy(a).to(dev) for a in (rp, ci, v))
+    bt = torch.from_numpy(b).to(dev)
+    prm = dict(WL.CONFIGS[2]["params"])
+    P = M.params(lu_update=args.lu_update, **prm)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        x, res, hist, rc = M.solve_csr(h, t_rp, t_ci, t_v, bt, P=P, x=x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        x, res, hist, rc = M.solve_csr(h, t_rp, t_ci, t_v, bt, P=P, x=x)
+        if rc != 0 or res.nbe > 1e-15:
+            print("sparse solve did not reach nbe <= 1e-15: rc=%d nbe=%.3e" % (rc, res.nbe), file=sys.stderr)
+            sys.exit(1)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    print(json.dumps({"metric": "solves/s to FP64 backward err 1e-15, sparse A (CSR)", "value": round(args.steps / el, 4),
+                      "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+                      "ms_per_step": round(1000.0 * el / args.steps, 3), "higher_is_better": True, "scaling": "weak",
+                      "vs_baseline": None, "dtype": "fp16-factor/fp32-working/fp64-residual (mixed)",
+                      "data": "synthetic sparse (seeded), float64",
+                      "config": {"workload": "msir_csr_n%d_nnz%d_per_row" % (n, per_row), "n": n, "nnz": int(len(v)),
+                                 "spread": scale},
+                      "history": M.render(hist), "nbe": res.nbe}))
+    h.close()
+
+
 def main():
     args = parse()
     if args.copy_only:
         copy_only(args.copy_only)
+        return
+    if args.sparse:
+        sparse_bench(args)
         return
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the solver is a single-device library; "

@@ -166,6 +166,19 @@ MSIR_API int msir_solve(msir_handle* h, int n, const double* dA, int lda, const 
                const double* dx_true, const msir_params* params, msir_result* out,
                msir_step* hist, int hist_cap, int* hist_len);
 
+/* Alg. 4 for a sparse A given in compressed sparse row form (Table 1's sparse
+ * case): drowptr n+1 int32 row pointers (drowptr[0] = 0, drowptr[n] = nnz,
+ * non-decreasing), dcolind nnz int32 column indices (strictly increasing within a
+ * row, in [0, n)), dvals nnz float64 values; all device arrays owned by the caller.
+ * The residual in u_r and A v inside GMRES use the CSR arrays (O(nnz) per product);
+ * the LU, the norms and the final error figures use a dense copy held by the handle
+ * (n^2 float64).  The pattern is validated on the device first: -12 when it is not
+ * a valid n x n CSR pattern (nothing else runs).  Other arguments, results and
+ * return values as for msir_solve.                                               */
+MSIR_API int msir_solve_csr(msir_handle* h, int n, int nnz, const int* drowptr, const int* dcolind,
+                   const double* dvals, const double* db, double* dx, const double* dx_true,
+                   const msir_params* params, msir_result* out, msir_step* hist, int hist_cap, int* hist_len);
+
 /* GMRES-IR5: the five-precision GMRES-based refinement of Sec. 1 (u_f, u, u_r,
  * u_g, u_p), without the multistage controller.  One LU in params->uf (scaling
  * policy params->scaling), x0 from the factors, then steps: r = b - A x in

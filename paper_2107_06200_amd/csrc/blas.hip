@@ -229,7 +229,7 @@ static int nsplit_for(int n) {
 int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
              double* rhat, double* s_dev, bool want_true) {
   const GemvPlan g = gemv_plan(n, 0);
-  const int ns = g.ns;
+  const int ns = c.sp ? 1 : g.ns;   // a sparse A gives one slice
   const int rb = (n + RT - 1) / RT;
   double* ph = c.ws_part_hi(ns * (size_t)n);
   double* pl = c.ws_part_lo(ns * (size_t)n);
@@ -239,7 +239,8 @@ int residual(Ctx& c, int n, const double* A, int lda, const double* x, const dou
   if (!ph || !pl || !px || !rh || !rl) return MSIR_ERR_ALLOC;
   const int mode = (ur == P_DD) ? 1 : (want_true ? 2 : 0);
   const int _slot = c.tbegin(MSIR_T_RESID);
-  int rc = gemv_partials(c, g, n, P_FP64, A, lda, x, nullptr, nullptr, mode, ph, pl, px, nullptr);
+  int rc = c.sp ? spmv_partials(c, n, *c.sp, false, x, nullptr, mode, ph, pl, px, nullptr)
+                : gemv_partials(c, g, n, P_FP64, A, lda, x, nullptr, nullptr, mode, ph, pl, px, nullptr);
   if (rc) return rc;
   if (mode == 1)
     k_resid_finish<1><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
@@ -256,15 +257,18 @@ int residual(Ctx& c, int n, const double* A, int lda, const double* x, const dou
 // y = A v with p in {FP32 (Au = fp32 copy of A), FP64, DD}; v holds values in u (float64 array).
 int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
            double* y_hi, double* y_lo, const int* skip, const int* operm, const double* oR) {
-  const GemvPlan g = gemv_plan(n, 0, p == P_FP32 ? P_FP32 : P_FP64, p == P_DD ? 1 : 0);
+  GemvPlan g = gemv_plan(n, 0, p == P_FP32 ? P_FP32 : P_FP64, p == P_DD ? 1 : 0);
+  if (c.sp) { g.ns = 1; g.chunk = n; }   // a sparse A gives one slice
   double* ph = c.ws_part_hi(g.ns * (size_t)n);
   double* pl = c.ws_part_lo(g.ns * (size_t)n);
   if (!ph || !pl) return MSIR_ERR_ALLOC;
-  int _slot = c.tbegin_kernel(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
+  int _slot = c.sp ? c.tbegin(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64)
+                   : c.tbegin_kernel(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
   int rc;
-  if (p == P_FP32) rc = gemv_partials(c, g, n, P_FP32, Au, ldau, v, nullptr, nullptr, 0, ph, pl, nullptr, skip);
+  if (c.sp) rc = spmv_partials(c, n, *c.sp, p == P_FP32, v, nullptr, p == P_DD ? 1 : 0, ph, pl, nullptr, skip);
+  else if (p == P_FP32) rc = gemv_partials(c, g, n, P_FP32, Au, ldau, v, nullptr, nullptr, 0, ph, pl, nullptr, skip);
   else rc = gemv_partials(c, g, n, P_FP64, A, lda, v, nullptr, nullptr, p == P_DD ? 1 : 0, ph, pl, nullptr, skip);
-  c.tend_kernel(_slot);
+  if (c.sp) c.tend(_slot); else c.tend_kernel(_slot);
   if (rc) return rc;
   _slot = c.tbegin(MSIR_T_FOLD);
   rc = gemv_finish(c, g, n, ph, pl, 1.0, nullptr, p, y_hi, y_lo, skip, operm, oR);

@@ -286,7 +286,9 @@ int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au
                  const double* Rp, int inv_prec, const void* X, const void* Y, double mu, const double* S, int u,
                  double* out, const int* skip) {
   if (p != P_FP32 && p != P_FP64) return -3;
-  const GemvPlan gm = gemv_plan(n, 0, p), gl = gemv_plan(n, 1, inv_prec), gu = gemv_plan(n, 2, inv_prec);
+  GemvPlan gm = gemv_plan(n, 0, p);
+  const GemvPlan gl = gemv_plan(n, 1, inv_prec), gu = gemv_plan(n, 2, inv_prec);
+  if (c.sp) { gm.ns = 1; gm.chunk = n; }   // a sparse A gives one slice
   double* pa = c.ws_part_hi((size_t)(gm.ns > gu.ns ? gm.ns : gu.ns) * n);
   double* pb = (double*)c.grow(c.tr_part, (size_t)gl.ns * n * sizeof(double));
   if (!pa || !pb) return MSIR_ERR_ALLOC;
@@ -295,10 +297,16 @@ int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au
     GemvIn in;
     in.x = v;
     in.prow = pinv;
-    const int slot = c.tbegin_kernel(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
-    if (p == P_FP32) rc = gemv_partials(c, gm, n, P_FP32, Au, n, in, 0, pa, nullptr, nullptr, skip);
-    else rc = gemv_partials(c, gm, n, P_FP64, A, lda, in, 0, pa, nullptr, nullptr, skip);
-    c.tend_kernel(slot);
+    if (c.sp) {
+      const int slot = c.tbegin(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
+      rc = spmv_partials(c, n, *c.sp, p == P_FP32, v, pinv, 0, pa, nullptr, nullptr, skip);
+      c.tend(slot);
+    } else {
+      const int slot = c.tbegin_kernel(p == P_FP32 ? MSIR_T_MATVEC : MSIR_T_MATVEC64);
+      if (p == P_FP32) rc = gemv_partials(c, gm, n, P_FP32, Au, n, in, 0, pa, nullptr, nullptr, skip);
+      else rc = gemv_partials(c, gm, n, P_FP64, A, lda, in, 0, pa, nullptr, nullptr, skip);
+      c.tend_kernel(slot);
+    }
     if (rc) return rc;
   }
   const int cls = inv_prec == P_FP32 ? MSIR_T_TRGEMV : MSIR_T_TRGEMV64;

@@ -248,7 +248,7 @@ struct msir_handle {
   Ctx c;
   GmresWork gw;
   FactorState f;
-  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Xd, Yd, Xf, Yf;
+  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Xd, Yd, Xf, Yf, Acsr;
   bool inv64 = false, inv32 = false;  // inverses of the current factorization are valid
   double* dev_small = nullptr;   // device scalars
   double* host_small = nullptr;  // pinned host scalars
@@ -479,7 +479,7 @@ int msir_destroy(msir_handle* h) {
   Ctx& c = h->c;
   DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.part_x, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
                     &c.tmp_scalar, &c.moved, &c.tr_part, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
-                    &h->tmp2, &h->Xd, &h->Yd, &h->Xf, &h->Yf};
+                    &h->tmp2, &h->Xd, &h->Yd, &h->Xf, &h->Yf, &h->Acsr};
   for (DevBuf* b : bufs) c.release(b->p, b->bytes);
   if (h->f.W) c.release(h->f.W, h->f.Wbytes);
   if (h->f.rinv) c.release(h->f.rinv, h->f.vec_bytes);
@@ -1390,6 +1390,37 @@ int msir_gmres_ir5(msir_handle* h, int n, const double* dA, int lda, const doubl
   }
   if (hist_len) *hist_len = (int)H.size();
   if (hist && hist_cap > 0) memcpy(hist, H.data(), std::min((size_t)hist_cap, H.size()) * sizeof(msir_step));
+  return rc;
+}
+
+int msir_solve_csr(msir_handle* h, int n, int nnz, const int* drowptr, const int* dcolind, const double* dvals,
+                   const double* db, double* dx, const double* dxt, const msir_params* params, msir_result* out,
+                   msir_step* hist, int hist_cap, int* hist_len) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (nnz < 0 || !drowptr || (nnz > 0 && (!dcolind || !dvals))) return -4;
+  if (!db) return -5;
+  if (!dx) return -6;
+  Ctx& c = h->c;
+  HIP_CHECK(hipSetDevice(c.device));
+  // validate the pattern before any kernel walks it
+  unsigned* flag = (unsigned*)(h->dev_small + 24);
+  int rc = csr_check(c, n, nnz, drowptr, dcolind, flag);
+  if (rc) return rc;
+  rc = sync_read(h, h->dev_small + 24, 1);
+  if (rc) return rc;
+  unsigned fl;
+  memcpy(&fl, &h->host_small[0], sizeof(fl));
+  if (fl) return -12;
+  Csr a;
+  a.nnz = nnz; a.rowptr = drowptr; a.colind = dcolind; a.vals = dvals;
+  double* Ad = (double*)c.grow(h->Acsr, (size_t)n * n * sizeof(double));
+  if (!Ad) return MSIR_ERR_ALLOC;
+  rc = csr_to_dense(c, n, a, Ad, n);
+  if (rc) return rc;
+  c.sp = &a;
+  rc = msir_solve(h, n, Ad, n, db, dx, dxt, params, out, hist, hist_cap, hist_len);
+  c.sp = nullptr;
   return rc;
 }
 

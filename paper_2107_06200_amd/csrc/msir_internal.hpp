@@ -15,6 +15,15 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// A sparse matrix in compressed sparse row form (device arrays): row i holds the
+// entries vals[k], columns colind[k], for k in [rowptr[i], rowptr[i+1]).
+struct Csr {
+  int nnz = 0;
+  const int* rowptr = nullptr;
+  const int* colind = nullptr;
+  const double* vals = nullptr;
+};
+
 struct Ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -58,6 +67,9 @@ struct Ctx {
   int ext_slot = -1;
   int tbegin_kernel(int cls);
   void tend_kernel(int slot);
+  // Sparse operand of the current solve (null: the dense A passed along is used):
+  // the residual and A v inside GMRES then run on the CSR arrays.
+  const Csr* sp = nullptr;
 };
 
 // Bracket a launch with timing events when enabled.
@@ -139,6 +151,14 @@ struct GemvPlan {
   int chunk = 1;   // columns per slice
   int nwg = 0;     // triangular: (row block, slice) pairs that meet the triangle
 };
+// CSR helpers (sparse.hip): validity check into *flag_dev (0 valid), densification into
+// a zero-filled column-major A, and one slice of partial sums of A x (modes as for
+// gemv_partials; f32: values rounded to float32; prow: output row map).
+int csr_check(Ctx& c, int n, int nnz, const int* rowptr, const int* colind, unsigned* flag_dev);
+int csr_to_dense(Ctx& c, int n, const Csr& a, double* A, int lda);
+int spmv_partials(Ctx& c, int n, const Csr& a, bool f32, const double* x, const int* prow, int mode, double* ph,
+                  double* pl, double* px, const int* skip);
+
 // Launch plan of a product with an n x n operand (tri 0 full, 1 lower, 2 upper) of
 // storage a_prec accumulated in mode (see gemv_partials).
 GemvPlan gemv_plan(int n, int tri, int a_prec = P_FP64, int mode = 0);

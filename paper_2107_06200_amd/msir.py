@@ -53,7 +53,7 @@ class Result(ctypes.Structure):
 
 
 SYMBOLS = ["msir_create", "msir_destroy", "msir_params_default", "msir_nb_auto", "msir_workspace_bytes",
-           "msir_status_string", "msir_solve", "msir_gmres_ir5", "msir_solve_multi", "msir_solve_batched", "msir_convert",
+           "msir_status_string", "msir_solve", "msir_solve_csr", "msir_gmres_ir5", "msir_solve_multi", "msir_solve_batched", "msir_convert",
            "msir_scaling", "msir_getrf", "msir_getrs", "msir_round", "msir_residual", "msir_gmres", "msir_backward_error",
            "msir_timing", "msir_timing_get"]
 
@@ -69,6 +69,8 @@ _SIG = {
     "msir_status_string": (ctypes.c_char_p, [_I]),
     "msir_solve": (_I, [_P, _I, _P, _I, _P, _P, _P, ctypes.POINTER(Params), ctypes.POINTER(Result),
                         ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
+    "msir_solve_csr": (_I, [_P, _I, _I, _P, _P, _P, _P, _P, _P, ctypes.POINTER(Params), ctypes.POINTER(Result),
+                            ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_gmres_ir5": (_I, [_P, _I, _P, _I, _P, _P, _P, ctypes.POINTER(Params), _I, _I, ctypes.POINTER(Result),
                             ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_solve_multi": (_I, [_P, _I, _I, _P, _I, _P, _I, _P, _I, ctypes.POINTER(Params), ctypes.POINTER(Result)]),
@@ -204,6 +206,26 @@ def solve(h, A, b, x_true=None, P=None, hist_cap=4096, x=None):
                           ctypes.byref(P) if P is not None else None, ctypes.byref(res), H, hist_cap,
                           ctypes.byref(hl))
     _check(rc, "msir_solve")
+    return x, res, [H[i] for i in range(min(hl.value, hist_cap))], rc
+
+
+def solve_csr(h, rowptr, colind, vals, b, x_true=None, P=None, hist_cap=4096, x=None):
+    """Alg. 4 with a sparse A in CSR form (int32 rowptr/colind, float64 vals, device
+    tensors).  Returns (x, Result, [Step...], status)."""
+    n = rowptr.shape[0] - 1
+    nnz = colind.shape[0]
+    for t, dt in ((rowptr, torch.int32), (colind, torch.int32), (vals, torch.float64)):
+        if t.dtype != dt or not t.is_contiguous():
+            raise ValueError("solve_csr: rowptr/colind int32, vals float64, contiguous")
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=b.device)
+    res = Result()
+    H = (Step * hist_cap)()
+    hl = ctypes.c_int(0)
+    rc = lib().msir_solve_csr(h.h, n, nnz, _ptr(rowptr), _ptr(colind), _ptr(vals), _ptr(b), _ptr(x), _ptr(x_true),
+                              ctypes.byref(P) if P is not None else None, ctypes.byref(res), H, hist_cap,
+                              ctypes.byref(hl))
+    _check(rc, "msir_solve_csr")
     return x, res, [H[i] for i in range(min(hl.value, hist_cap))], rc
 
 

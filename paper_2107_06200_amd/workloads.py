@@ -112,3 +112,39 @@ def serving_requests(count=2000, sizes=(256, 512, 1024, 2048, 4096), seed=5, rat
 
 def request_system(req, seed=5):
     return randsvd(req["n"], req["kappa"], req["mode"], rng_for(seed, req["id"]), nrhs=req["nrhs"])
+
+
+def sparse_system(n, per_row, scale, rng):
+    """Synthetic sparse system standing in for the paper's sparse test matrices.
+
+    Each row holds its diagonal and per_row - 1 off-diagonal entries at random
+    distinct columns (N(0, 1) values); the diagonal is (1.5 + U[0, 1]) sqrt(per_row - 1),
+    which keeps the pattern matrix reasonably conditioned.  Rows and columns are then
+    scaled by scale**U[0, 1] (independent per row and per column), which spreads the
+    magnitudes and raises the condition number up to about scale^2 times.
+    Returns (rowptr int32 n+1, colind int32 nnz, vals float64 nnz, A dense float64,
+    x_true, b = A x_true).
+    """
+    k = per_row - 1
+    cols = np.empty((n, per_row), dtype=np.int64)
+    vals = rng.standard_normal((n, per_row))
+    for i in range(n):
+        c = rng.choice(n - 1, size=k, replace=False)
+        c[c >= i] += 1
+        cols[i, 0] = i
+        cols[i, 1:] = c
+        vals[i, 0] = (1.5 + rng.random()) * math.sqrt(max(k, 1))
+    order = np.argsort(cols, axis=1)
+    cols = np.take_along_axis(cols, order, axis=1)
+    vals = np.take_along_axis(vals, order, axis=1)
+    dr = scale ** rng.random(n)
+    dc = scale ** rng.random(n)
+    vals = vals * dr[:, None] * dc[cols]
+    rowptr = (np.arange(n + 1) * per_row).astype(np.int32)
+    colind = cols.reshape(-1).astype(np.int32)
+    v = vals.reshape(-1).astype(np.float64)
+    A = np.zeros((n, n))
+    A[np.repeat(np.arange(n), per_row), colind] = v
+    x = rng.standard_normal(n)
+    b = A @ x
+    return rowptr, colind, v, A, x, b

@@ -3,6 +3,8 @@
 import os
 import re
 
+import numpy as np
+
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -57,3 +59,20 @@ def test_panel_width_rule_agrees_with_oracle():
     for n in (1, 64, 100, 1024, 1025, 2048, 3000, 4096, 5000, 8192):
         for fmt in ("fp16", "bf16", "fp32", "fp64"):
             assert M.nb_auto(n, fmt) == OLU.nb_auto(n, fmt), (n, fmt)
+
+
+def test_sparse_workload_is_valid_csr():
+    # the synthetic sparse inputs: valid CSR (row pointers, sorted distinct columns in
+    # range, diagonal present) that equals the dense matrix the oracle uses
+    from paper_2107_06200_amd import workloads as WL
+    rp, ci, v, A, x, b = WL.sparse_system(200, 6, 10.0, WL.rng_for(51, 200))
+    n = 200
+    assert rp[0] == 0 and rp[-1] == len(ci) == len(v) and np.all(np.diff(rp) >= 0)
+    for i in range(n):
+        cols = ci[rp[i]:rp[i + 1]]
+        assert np.all(np.diff(cols) > 0) and cols.min() >= 0 and cols.max() < n and i in cols
+    D = np.zeros((n, n))
+    for i in range(n):
+        D[i, ci[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    assert np.array_equal(D, A)
+    assert np.allclose(A @ x, b)

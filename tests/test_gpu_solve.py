@@ -222,3 +222,35 @@ def test_gmres_ir5_vs_oracle(M, h, combo, n, kappa, mode):
     kinf = WL.kappa_inf(A)
     tol = max(1e-12 * max(1.0, kappa * 1e-4), 4 * kinf * (res.nbe + ref.nbe))
     assert np.abs(xg.cpu().numpy() - ref.x).max() <= tol * np.abs(ref.x).max()
+
+
+@pytest.mark.parametrize("n,k,scale,cfg", [(300, 8, 10.0, 1), (1000, 16, 300.0, 2), (1000, 16, 3000.0, 2)])
+def test_sparse_csr_vs_oracle(M, h, n, k, scale, cfg):
+    # Table 1's sparse case: the residual and A v inside GMRES run on the CSR arrays
+    # (O(nnz)); same history as the oracle on the equivalent dense matrix, nbe <= 1e-15
+    rp, ci, v, A, x, b = WL.sparse_system(n, k, scale, WL.rng_for(51, n))
+    prm = dict(WL.CONFIGS[cfg]["params"])
+    xg, res, hist, rc = M.solve_csr(h, torch.from_numpy(rp).to(DEV), torch.from_numpy(ci).to(DEV),
+                                    torch.from_numpy(v).to(DEV), torch.from_numpy(b).to(DEV),
+                                    x_true=torch.from_numpy(x).to(DEV), P=M.params(lu_update="fma", **prm))
+    ref = OM.msir(A, b, OM.Params(**prm), x_true=x)
+    print("gpu", M.render(hist), "nbe %.2e" % res.nbe, "| oracle", OM.render(ref.history), "nbe %.2e" % ref.nbe)
+    assert_same_history(hist, ref)
+    assert rc == 0 and res.cged == 1 and res.nbe <= 1e-15
+    assert OMET.nbe(A, xg.cpu().numpy(), b) <= 1e-15
+    kinf = WL.kappa_inf(A)
+    tol = max(1e-12, 4 * kinf * (res.nbe + ref.nbe))
+    assert np.abs(xg.cpu().numpy() - ref.x).max() <= tol * np.abs(ref.x).max()
+
+
+def test_sparse_csr_invalid_pattern_rejected(M, h):
+    # the device check turns an invalid pattern into an error before any kernel walks it
+    rp, ci, v, A, x, b = WL.sparse_system(64, 4, 2.0, WL.rng_for(52, 0))
+    bad_rp = rp.copy()
+    bad_rp[10] = bad_rp[11] + 1          # decreasing row pointers
+    bad_ci = ci.copy()
+    bad_ci[5] = 64                        # column out of range
+    for r, c in ((bad_rp, ci), (rp, bad_ci)):
+        with pytest.raises(M.MsirError, match="-12"):
+            M.solve_csr(h, torch.from_numpy(r).to(DEV), torch.from_numpy(c).to(DEV), torch.from_numpy(v).to(DEV),
+                        torch.from_numpy(b).to(DEV))
