@@ -309,6 +309,57 @@ def test_getrs_dd_vs_oracle(M, h):
     assert np.abs(diff).max() <= 2.0 ** -98 * np.abs(hi).max()
 
 
+def multiblock_factors(n, fmt, seed):
+    """Stored factors for solves over many 64-row blocks without running the oracle's
+    elimination: the strict lower part is L, the upper part U (diagonal bounded away from
+    zero, off-diagonal entries of size 1/sqrt(n)), random LAPACK-style interchanges."""
+    rng = np.random.default_rng(seed)
+    W = rng.standard_normal((n, n)) / np.sqrt(n)
+    W[np.diag_indices(n)] = (1.0 + np.abs(rng.standard_normal(n))) * np.where(rng.random(n) < 0.5, -1.0, 1.0)
+    W = F.round_to(W, fmt)
+    piv = np.array([rng.integers(j, n) for j in range(n)], dtype=np.int64)
+    return W, piv
+
+
+@pytest.mark.parametrize("fmt,comp", [("fp16", "fp16"), ("bf16", "bf16"), ("fp16", "fp64"), ("fp32", "fp32"),
+                                      ("fp64", "fp64")])
+@pytest.mark.parametrize("n", [200, 449, 1000])
+def test_getrs_multiblock_vs_oracle(M, h, fmt, comp, n):
+    # several 64-row blocks and a ragged last block: the chain, the helper sums of older
+    # blocks and the forward/backward hand-over all take part
+    W, piv = multiblock_factors(n, fmt, 31 + n)
+    rng = np.random.default_rng(7 + n)
+    t = rng.standard_normal(n)
+    scal = (rng.uniform(0.5, 2.0, n), rng.uniform(0.5, 2.0, n), 0.75) if fmt == "fp16" else None
+    want = OSV.lu_solve(W, piv, t, comp, scal)
+    Wd = to_dev_fmt(W, fmt, M)
+    ip = torch.from_numpy(piv.astype(np.int32)).to(DEV)
+    R = S = None
+    mu = 1.0
+    if scal is not None:
+        R, S, mu = tdev(scal[0]), tdev(scal[1]), scal[2]
+    got = M.getrs(h, Wd, fmt, ip, tdev(t), comp, R, S, mu).cpu().numpy()
+    assert np.all(np.isfinite(want))
+    if comp == "fp64":
+        np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * np.abs(want).max())
+    else:
+        mism = np.mean(got != want)
+        assert mism <= 0.02, mism
+        assert np.abs(got - want).max() <= 64 * F.u(comp) * np.abs(want).max()
+
+
+@pytest.mark.parametrize("n", [300, 449])
+def test_getrs_dd_multiblock_vs_oracle(M, h, n):
+    W, piv = multiblock_factors(n, "fp64", 41 + n)
+    t = np.random.default_rng(8 + n).standard_normal(n)
+    hi, lo = OSV.lu_solve(W, piv, t, "dd")
+    Wd = to_dev_fmt(W, "fp64", M)
+    ip = torch.from_numpy(piv.astype(np.int32)).to(DEV)
+    y = M.getrs(h, Wd, "fp64", ip, tdev(np.concatenate([t, np.zeros(n)])), "dd").cpu().numpy()
+    diff = (y[:n] - hi) + (y[n:] - lo)
+    assert np.abs(diff).max() <= 2.0 ** -96 * np.abs(hi).max()
+
+
 def test_getrs_fp16_overflow_gives_inf(M, h):
     # u_f = fp16 solve: components beyond 65504 become Inf (the Alg. 4 NaN check relies on it)
     W = np.array([[2.0 ** -10, 0.0], [0.0, 1.0]])
