@@ -228,7 +228,7 @@ def test_getrf_exact_arithmetic_bitexact(M, h, fmt, n, nb):
 
 
 @pytest.mark.parametrize("fmt,n,nb", [("fp16", 200, 64), ("fp16", 333, 16), ("bf16", 200, 32), ("fp16", 1100, 32),
-                                      ("fp32", 257, 16)])
+                                      ("fp32", 257, 16), ("fp16", 1100, 16), ("bf16", 600, 8)])
 def test_getrf_fma_update_bitexact(M, h, fmt, n, nb):
     """Reproducible trailing update (sequential fp32 FMA over k): the whole blocked
     factorization -- panel, interchanges, U12, trailing updates -- must equal the
@@ -241,6 +241,30 @@ def test_getrf_fma_update_bitexact(M, h, fmt, n, nb):
     assert info == io
     np.testing.assert_array_equal(ipiv.cpu().numpy(), po)
     np.testing.assert_array_equal(host_w(W, fmt), Wo)
+
+
+@pytest.mark.parametrize("fmt,n,nb", [("fp16", 3000, 16), ("fp32", 2500, 16), ("fp64", 1800, 16), ("fp64", 3000, 8)])
+def test_getrf_tall_panels_backward_error(M, h, fmt, n, nb):
+    """Panels of more than 2048 rows (up to four rows per panel thread): checked by
+    properties that hold at any size (the oracle's elimination is too slow here):
+    componentwise backward error |PA - LU| <= gamma |L||U|, |L| <= 1 (partial
+    pivoting), LAPACK-style pivots, every entry representable in u_f."""
+    rng = np.random.default_rng(n + 3 * nb)
+    Af = F.round_to(rng.standard_normal((n, n)), fmt)
+    W = to_dev_fmt(Af, fmt, M)
+    ipiv, info = M.getrf(h, W, fmt, nb)
+    assert info == 0
+    Wg = host_w(W, fmt)
+    np.testing.assert_array_equal(F.round_to(Wg, fmt), Wg)
+    piv = ipiv.cpu().numpy()
+    assert np.all(piv >= np.arange(n)) and np.all(piv < n)
+    L, U = OLU.unpack(Wg)
+    assert np.abs(np.tril(L, -1)).max() <= 1.0
+    p = OLU.perm_from_piv(piv)
+    E = np.abs(Af[p] - L @ U)
+    ua = F.u("fp64") if fmt == "fp64" else F.u("fp32")
+    g = (n / nb + n * ua / F.u(fmt) + 3) * F.u(fmt)
+    assert np.all(E <= g / (1 - g) * (np.abs(L) @ np.abs(U)) + 1e-300)
 
 
 def test_getrf_zero_pivot_info(M, h):
