@@ -148,9 +148,8 @@ __device__ __forceinline__ K wave_max_key(K x) {
 }
 
 template <int P, int R, int NB>
-__global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
-                                               int* __restrict__ ipiv, int* __restrict__ info,
-                                               int* __restrict__ moved) {
+__device__ __forceinline__ void panel_body(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
+                                           int* __restrict__ ipiv, int* __restrict__ info, int* __restrict__ moved) {
   typedef typename Arith<P>::T AT;
   typedef PivKey<AT> K;
   const int tid = threadIdx.x;
@@ -292,6 +291,13 @@ __global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict_
   }
   __syncthreads();
   if (tid == 0) moved[0] = s_cnt;
+}
+
+template <int P, int R, int NB>
+__global__ __launch_bounds__(PNT) void k_panel(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
+                                               int* __restrict__ ipiv, int* __restrict__ info,
+                                               int* __restrict__ moved) {
+  panel_body<P, R, NB>(W, ldw, n, j0, jb, ipiv, info, moved);
 }
 
 // ------------------------------------------------------------------ interchanges + U12
@@ -499,16 +505,19 @@ __device__ __forceinline__ float16_t mfma_32x32x8(const uint16_t* a4, const uint
   }
 }
 
+// One output tile (tile row bx, tile column by of the trailing matrix) by 256 threads
+// t = 0..255; sA / sB: the tile's LDS.  Tiles outside the matrix load and store
+// nothing but still take part in the barrier.
 template <int P, int KMAX, bool MF>
-__global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb) {
+__device__ __forceinline__ void gemm_tile(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb, int bx,
+                                          int by, int tid, typename Store<P>::T (*sA)[KMAX + 4],
+                                          typename Store<P>::T (*sB)[KMAX + 4]) {
   typedef typename Arith<P>::T AT;
   typedef typename Store<P>::T ST;
-  const int tid = threadIdx.x;
   const int jr = j0 + jb;
-  const int r0 = jr + blockIdx.x * GT;
-  const int c0 = jr + blockIdx.y * GT;
-  __shared__ ST sA[GT][KMAX + 4];   // L21 tile, [row][k]
-  __shared__ ST sB[GT][KMAX + 4];   // U12 tile, [col][k]
+  const int r0 = jr + bx * GT;
+  const int c0 = jr + by * GT;
+  // sA: L21 tile, [row][k]; sB: U12 tile, [col][k]
   // stage L21: column k of the tile is 64 contiguous rows (k >= jb zero-filled: the
   // matrix-core paths consume k in steps of 8 or 2)
   for (int e = tid; e < GT * KMAX; e += GNT) {
@@ -660,6 +669,32 @@ __global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__
   }
 }
 
+// Trailing update on tile columns ct0 .. ct0 + gridDim.y - 1.
+template <int P, int KMAX, bool MF>
+__global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0, int jb,
+                                              int ct0) {
+  __shared__ typename Store<P>::T sA[GT][KMAX + 4], sB[GT][KMAX + 4];
+  gemm_tile<P, KMAX, MF>(W, ldw, n, j0, jb, blockIdx.x, ct0 + blockIdx.y, threadIdx.x, sA, sB);
+}
+
+// Look-ahead: workgroup 0 factors the next panel (block j0p, whose columns the
+// previous launch updated) while the others apply the current block's trailing update
+// to tile columns 1, 2, ... (the columns right of the next panel's tile column), four
+// 64 x 64 tiles per workgroup of 1024 threads.  The two parts touch disjoint columns.
+template <int P, int R, int NB, bool MF>
+__global__ __launch_bounds__(PNT) void k_panel_gemm(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0p,
+                                                    int jbp, int* __restrict__ ipiv, int* __restrict__ info,
+                                                    int* __restrict__ moved, int j0, int jb, int mtiles) {
+  if (blockIdx.x == 0) {
+    panel_body<P, R, NB>(W, ldw, n, j0p, jbp, ipiv, info, moved);
+    return;
+  }
+  __shared__ typename Store<P>::T sA[PNT / GNT][GT][NB + 4], sB[PNT / GNT][GT][NB + 4];
+  const int sub = threadIdx.x / GNT;
+  const int tile = (blockIdx.x - 1) * (PNT / GNT) + sub;
+  gemm_tile<P, NB, MF>(W, ldw, n, j0, jb, tile % mtiles, 1 + tile / mtiles, threadIdx.x % GNT, sA[sub], sB[sub]);
+}
+
 // ------------------------------------------------------------------ driver
 template <int P, int R, int NB>
 static void launch_panel(Ctx& c, void* W, int ldw, int n, int j0, int jb, int* ipiv, int* info, int* moved) {
@@ -677,13 +712,48 @@ static void panel_dispatch(Ctx& c, void* W, int ldw, int n, int j0, int jb, int*
   else launch_panel<P, (8 * NB <= CAP ? 8 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
 }
 
+template <int P, int R, int NB, bool MF>
+static void launch_panel_gemm(Ctx& c, void* W, int ldw, int n, int j0p, int jbp, int* ipiv, int* info, int* moved,
+                              int j0, int jb, int mtiles) {
+  const int tiles = mtiles * (mtiles - 1);   // tile columns 1 .. mtiles-1
+  const int grid = 1 + (tiles + PNT / GNT - 1) / (PNT / GNT);
+  k_panel_gemm<P, R, NB, MF><<<grid, PNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0p, jbp, ipiv, info,
+                                                         moved, j0, jb, mtiles);
+}
+
+template <int P, int NB, bool MF>
+static void panel_gemm_dispatch(Ctx& c, void* W, int ldw, int n, int j0p, int jbp, int* ipiv, int* info, int* moved,
+                                int j0, int jb, int mtiles) {
+  const int m = n - j0p;
+  const int R = (m + PNT - 1) / PNT;
+  constexpr int CAP = (P == P_FP64) ? 32 : 64;
+  if (R <= 1) launch_panel_gemm<P, 1, NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
+  else if (R <= 2 && 2 * NB <= CAP) launch_panel_gemm<P, (2 * NB <= CAP ? 2 : 1), NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
+  else if (R <= 4 && 4 * NB <= CAP) launch_panel_gemm<P, (4 * NB <= CAP ? 4 : 1), NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
+  else launch_panel_gemm<P, (8 * NB <= CAP ? 8 : 1), NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
+}
+
+// LDS of the look-ahead launch: four GEMM tiles plus the panel's exchange buffers.
+template <int P, int NB>
+constexpr bool fuse_fits() {
+  return (PNT / GNT) * 2 * GT * (NB + 4) * sizeof(typename Store<P>::T) +
+             (2 * (PNT / 64) * NB + NB * NB) * sizeof(typename Arith<P>::T) + 1024 <=
+         160 * 1024;
+}
+
+// Blocked elimination with a look-ahead of one panel: after block j0's interchanges
+// and U12, its trailing update runs first on the tile column holding the next panel,
+// then the next panel is factored in the same launch as the rest of the update
+// (configurations whose look-ahead launch would not fit the LDS keep the plain order).
 template <int P, int NB>
 static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info, bool mfma) {
   int* moved = (int*)c.grow(c.moved, (2 * MAXMOVE + 4) * sizeof(int));
   if (!moved) return MSIR_ERR_ALLOC;
+  bool factored = false;   // the panel of block j0 was factored by the previous launch
   for (int j0 = 0; j0 < n; j0 += NB) {
     const int jb = (n - j0 < NB) ? n - j0 : NB;
-    MSIR_TIMED(c, 0, (panel_dispatch<P, NB>(c, W, ldw, n, j0, jb, ipiv, info, moved)));
+    if (!factored) MSIR_TIMED(c, 0, (panel_dispatch<P, NB>(c, W, ldw, n, j0, jb, ipiv, info, moved)));
+    factored = false;
     const int others = n - jb;
     if (others > 0) {
       if constexpr (NB <= 32 && (NB * sizeof(typename Store<P>::T)) % 16 == 0)
@@ -694,10 +764,26 @@ static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info, bool 
                              (typename Store<P>::T*)W, ldw, n, j0, jb, moved)));
     }
     const int mt = n - j0 - jb;
-    if (mt > 0) {
+    if (mt > 0 && !fuse_fits<P, NB>()) {
       dim3 g((mt + GT - 1) / GT, (mt + GT - 1) / GT);
-      if (mfma) MSIR_TIMED(c, 2, (k_gemm<P, NB, true><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb)));
-      else MSIR_TIMED(c, 2, (k_gemm<P, NB, false><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb)));
+      if (mfma) MSIR_TIMED(c, 2, (k_gemm<P, NB, true><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
+      else MSIR_TIMED(c, 2, (k_gemm<P, NB, false><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
+    } else if (mt > 0) {
+      const int mtiles = (mt + GT - 1) / GT;
+      const int j1 = j0 + jb, jb1 = (n - j1 < NB) ? n - j1 : NB;
+      // tile column 0 of the update (it holds the next panel's columns)
+      if (mfma) MSIR_TIMED(c, 2, (k_gemm<P, NB, true><<<dim3(mtiles, 1), GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
+      else MSIR_TIMED(c, 2, (k_gemm<P, NB, false><<<dim3(mtiles, 1), GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
+      if (mtiles > 1) {
+        // the next panel and the rest of the update
+        if constexpr (fuse_fits<P, NB>()) {
+          if (mfma) MSIR_TIMED(c, 0, (panel_gemm_dispatch<P, NB, true>(c, W, ldw, n, j1, jb1, ipiv, info, moved, j0, jb, mtiles)));
+          else MSIR_TIMED(c, 0, (panel_gemm_dispatch<P, NB, false>(c, W, ldw, n, j1, jb1, ipiv, info, moved, j0, jb, mtiles)));
+        }
+      } else {
+        MSIR_TIMED(c, 0, (panel_dispatch<P, NB>(c, W, ldw, n, j1, jb1, ipiv, info, moved)));
+      }
+      factored = true;
     }
   }
   HIP_CHECK(hipGetLastError());

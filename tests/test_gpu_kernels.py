@@ -173,7 +173,7 @@ def test_getrf_manufactured_pivots_bitexact(M, h, fmt, n, nb):
 
 
 @pytest.mark.parametrize("fmt,n,nb", [("fp16", 200, 64), ("fp16", 333, 16), ("bf16", 200, 32),
-                                      ("fp32", 200, 16), ("fp64", 150, 16)])
+                                      ("fp32", 200, 16), ("fp64", 150, 16), ("fp32", 300, 64), ("fp64", 300, 32)])
 def test_getrf_blocked_vs_oracle(M, h, fmt, n, nb):
     rng = np.random.default_rng(n + nb)
     Af = F.round_to(rng.standard_normal((n, n)), fmt)
@@ -228,7 +228,7 @@ def test_getrf_exact_arithmetic_bitexact(M, h, fmt, n, nb):
 
 
 @pytest.mark.parametrize("fmt,n,nb", [("fp16", 200, 64), ("fp16", 333, 16), ("bf16", 200, 32), ("fp16", 1100, 32),
-                                      ("fp32", 257, 16), ("fp16", 1100, 16), ("bf16", 600, 8)])
+                                      ("fp32", 257, 16), ("fp16", 1100, 16), ("bf16", 600, 8), ("fp32", 300, 64)])
 def test_getrf_fma_update_bitexact(M, h, fmt, n, nb):
     """Reproducible trailing update (sequential fp32 FMA over k): the whole blocked
     factorization -- panel, interchanges, U12, trailing updates -- must equal the
