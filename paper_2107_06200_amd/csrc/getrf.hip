@@ -517,21 +517,31 @@ __device__ __forceinline__ void gemm_tile(typename Store<P>::T* __restrict__ W, 
   const int jr = j0 + jb;
   const int r0 = jr + bx * GT;
   const int c0 = jr + by * GT;
-  // sA: L21 tile, [row][k]; sB: U12 tile, [col][k]
-  // stage L21: column k of the tile is 64 contiguous rows (k >= jb zero-filled: the
-  // matrix-core paths consume k in steps of 8 or 2)
-  for (int e = tid; e < GT * KMAX; e += GNT) {
-    const int i = e % GT, k = e / GT;
-    const int r = r0 + i;
-    sA[i][k] = (r < n && k < jb) ? W[(size_t)(j0 + k) * ldw + r] : (ST)0;
+  // sA: L21 tile, [row][k]; sB: U12 tile, [col][k].  L21: column k of the tile is 64
+  // contiguous rows; U12: column c of the tile holds jb contiguous values (k >= jb
+  // zero-filled: the matrix-core paths consume k in steps of 8 or 2).  The loads are
+  // unconditional (indices clamped into the matrix, masked when stored), so that all
+  // of them are in flight together; stage_st writes them after the output tile's own
+  // loads have been issued.
+  constexpr int SI = GT * KMAX / GNT;
+  ST va[SI], vb[SI];
+#pragma unroll
+  for (int it = 0; it < SI; ++it) {
+    const int e = tid + it * GNT;
+    va[it] = W[(size_t)(j0 + min(e / GT, jb - 1)) * ldw + min(r0 + e % GT, n - 1)];
+    vb[it] = W[(size_t)min(c0 + e / KMAX, n - 1) * ldw + j0 + min(e % KMAX, jb - 1)];
   }
-  // stage U12: column c of the tile holds jb contiguous values
-  for (int e = tid; e < GT * KMAX; e += GNT) {
-    const int k = e % KMAX, q = e / KMAX;
-    const int c = c0 + q;
-    sB[q][k] = (c < n && k < jb) ? W[(size_t)c * ldw + j0 + k] : (ST)0;
-  }
-  __syncthreads();
+  auto stage_st = [&]() {
+#pragma unroll
+    for (int it = 0; it < SI; ++it) {
+      const int e = tid + it * GNT;
+      const int i = e % GT, ka = e / GT;
+      sA[i][ka] = (r0 + i < n && ka < jb) ? va[it] : (ST)0;
+      const int kb = e % KMAX, q = e / KMAX;
+      sB[q][kb] = (c0 + q < n && kb < jb) ? vb[it] : (ST)0;
+    }
+    __syncthreads();
+  };
   if constexpr ((P == P_FP16 || P == P_BF16) && MF) {
     const int lane = tid & 63, wv = tid >> 6;
     const int lc = lane & 31, hi = lane >> 5;
@@ -559,6 +569,7 @@ __device__ __forceinline__ void gemm_tile(typename Store<P>::T* __restrict__ W, 
         }
       }
     }
+    stage_st();
 #pragma unroll
     for (int kk = 0; kk < KMAX; kk += 8) {
       if (kk < jb) {
@@ -613,6 +624,7 @@ __device__ __forceinline__ void gemm_tile(typename Store<P>::T* __restrict__ W, 
           acc[4 * g + e] = (col < n && r < n) ? W[(size_t)col * ldw + r] : 0.0f;
         }
     }
+    stage_st();
 #pragma unroll
     for (int kk = 0; kk < KMAX; kk += 2) {
       if (kk < jb) {
@@ -646,8 +658,10 @@ __device__ __forceinline__ void gemm_tile(typename Store<P>::T* __restrict__ W, 
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int r = r0 + ty + 16 * i, c = c0 + tx + 16 * j;
-        acc[i][j] = (r < n && c < n) ? to_a<P>(W[(size_t)c * ldw + r], AT(0)) : AT(0);
+        const AT v = to_a<P>(W[(size_t)min(c, n - 1) * ldw + min(r, n - 1)], AT(0));
+        acc[i][j] = (r < n && c < n) ? v : AT(0);
       }
+    stage_st();
     for (int k = 0; k < jb; ++k) {
       AT a[4], b[4];
 #pragma unroll
