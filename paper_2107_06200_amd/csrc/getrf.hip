@@ -397,24 +397,38 @@ __global__ __launch_bounds__(SNT) void k_swap_trsm_v(typename Store<P>::T* __res
   const int jr = j0 + jb;
   __shared__ int s_src[KMAX];                  // source row of block row k
   __shared__ int s_odst[KMAX], s_osrc[KMAX];   // outside destinations, their block sources
-  __shared__ int s_cnt, s_nout;
+  __shared__ int s_nout;
   __shared__ AT sL[KMAX][KMAX + 1];
   __shared__ AT sb[KMAX][SNT];                 // this workgroup's block rows, one column per lane
-  if (tid == 0) { s_cnt = moved[0]; s_nout = 0; }
+  // (1) the list's count and entries and L11, all loads in flight together (entries
+  // past the count and L11 entries outside the block come from clamped addresses and
+  // are ignored)
+  static_assert(MM <= SNT, "one list entry per thread");
+  constexpr int LI = (KMAX * KMAX + SNT - 1) / SNT;
+  const int cnt_all = moved[0];
+  const int mdst = moved[1 + 2 * min(tid, MM - 1)], msrc = moved[2 + 2 * min(tid, MM - 1)];
+  ST lraw[LI];
+#pragma unroll
+  for (int it = 0; it < LI; ++it) {
+    const int e = min(tid + it * SNT, KMAX * KMAX - 1);
+    lraw[it] = W[(size_t)(j0 + min(e / KMAX, jb - 1)) * ldw + j0 + min(e % KMAX, jb - 1)];
+  }
+  if (tid == 0) s_nout = 0;
   for (int k = tid; k < KMAX; k += SNT) s_src[k] = j0 + k;
-  for (int e = tid; e < KMAX * KMAX; e += SNT) {
+#pragma unroll
+  for (int it = 0; it < LI; ++it) {
+    const int e = tid + it * SNT;
     const int i = e % KMAX, k = e / KMAX;
-    sL[i][k] = (i < jb && k < jb) ? to_a<P>(W[(size_t)(j0 + k) * ldw + j0 + i], AT(0)) : AT(0);
+    if (e < KMAX * KMAX) sL[i][k] = (i < jb && k < jb) ? to_a<P>(lraw[it], AT(0)) : AT(0);
   }
   __syncthreads();
-  const int cnt = min(s_cnt, MM);
-  for (int i = tid; i < cnt; i += SNT) {
-    const int d = moved[1 + 2 * i], sr = moved[2 + 2 * i];
-    if (d >= j0 && d < jr) {
-      s_src[d - j0] = sr;
+  const int cnt = min(cnt_all, MM);
+  if (tid < cnt) {
+    if (mdst >= j0 && mdst < jr) {
+      s_src[mdst - j0] = msrc;
     } else {
       const int q = atomicAdd(&s_nout, 1);
-      if (q < KMAX) { s_odst[q] = d; s_osrc[q] = sr; }
+      if (q < KMAX) { s_odst[q] = mdst; s_osrc[q] = msrc; }
     }
   }
   __syncthreads();
@@ -434,12 +448,14 @@ __global__ __launch_bounds__(SNT) void k_swap_trsm_v(typename Store<P>::T* __res
     __builtin_memcpy(blk, raw, sizeof(blk));
   } else {
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) blk[k] = (k < jb) ? w[j0 + k] : ST(0);
+    for (int k = 0; k < KMAX; ++k) blk[k] = w[min(j0 + min(k, jb - 1), n - 1)];   // k >= jb: not used
   }
+  // outside sources: every load unconditional (row j0 + k when the row is not moved in
+  // from outside; that value is not used), so none waits for another
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     const int sr = s_src[k];
-    ext[k] = (k < jb && sr >= jr) ? w[sr] : ST(0);
+    ext[k] = w[(k < jb && sr >= jr) ? sr : j0 + min(k, jb - 1)];
   }
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) sb[k][tid] = to_a<P>(blk[k], AT(0));
