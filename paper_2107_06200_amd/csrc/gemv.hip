@@ -48,10 +48,23 @@ __device__ __forceinline__ int lane_row(int lane, int e) {
 
 // One column's four entries for this lane, in the matrix's own type.  `pc` is the
 // column, rA / rB the first rows of the lane's row groups (rB only for fp64) and
-// vA / vB how many rows of each group exist; missing rows read as zero.
-template <typename TA>
+// vA / vB how many rows of each group exist; missing rows read as zero.  ALLVEC: the
+// caller knows that every lane takes the 16-byte path (no branch around the loads, so
+// that loads kept in flight across iterations are not waited for at a join).
+template <typename TA, bool ALLVEC>
 __device__ __forceinline__ void load_col4(const TA* __restrict__ pc, int rA, int rB, int vA, int vB, bool vec,
                                           TA v[4]) {
+  if constexpr (ALLVEC) {
+    if constexpr (sizeof(TA) == 4) {
+      const float4 q = *reinterpret_cast<const float4*>(pc + rA);
+      v[0] = q.x; v[1] = q.y; v[2] = q.z; v[3] = q.w;
+    } else {
+      const double2 q0 = *reinterpret_cast<const double2*>(pc + rA);
+      const double2 q1 = *reinterpret_cast<const double2*>(pc + rB);
+      v[0] = q0.x; v[1] = q0.y; v[2] = q1.x; v[3] = q1.y;
+    }
+    return;
+  }
   if constexpr (sizeof(TA) == 4) {
     if (vec) {
       const float4 q = *reinterpret_cast<const float4*>(pc + rA);
@@ -157,15 +170,19 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   double xs[XPT];
   const int sub = in.xpart ? min(8, max(1, GV_T / len)) : 1;
   if (!in.xpart) {
+    int pq[XPT];
 #pragma unroll
-    for (int q = 0; q < XPT; ++q) {
-      const int jj = j0 + min(tid + q * GV_T, len - 1);
-      if (in.perm) {
-        const int pq = in.perm[jj];
-        xs[q] = in.R ? in.R[pq] * in.x[pq] : in.x[pq];
-      } else {
-        xs[q] = in.x[jj];
-      }
+    for (int q = 0; q < XPT; ++q) pq[q] = j0 + min(tid + q * GV_T, len - 1);
+    if (in.perm) {
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) pq[q] = in.perm[pq[q]];   // all index loads in flight together
+    }
+    if (in.R) {
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) xs[q] = in.R[pq[q]] * in.x[pq[q]];
+    } else {
+#pragma unroll
+      for (int q = 0; q < XPT; ++q) xs[q] = in.x[pq[q]];
     }
   } else if (tid < sub * len) {
     const int e = tid % len, k = tid / len;
@@ -191,11 +208,17 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   constexpr int UNR = (sizeof(TA) == 4 || (MODE == 0 && TRI == 0)) ? 8 : 4;   // columns in flight per lane
   static_assert(UNR * GV_WAVES <= GV_BATCH && GV_BATCH % (UNR * GV_WAVES) == 0, "slices must be whole batches");
   constexpr int STEP = UNR * GV_WAVES;   // columns a workgroup consumes per batch
+  double h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0}, f[4] = {0, 0, 0, 0};
+  // Sections 2-4 are instantiated twice: for workgroups whose 256 rows all lie inside
+  // the matrix (aligned), with branch-free 16-byte loads, and for the rest.
+  auto body = [&](auto allvec_tag) {
+  constexpr bool ALLVEC = decltype(allvec_tag)::value;
   TA va[UNR][4];
   int j = j0 + w;
   auto load_batch = [&](TA (&vv)[UNR][4], int jj) {
 #pragma unroll
-    for (int u = 0; u < UNR; ++u) load_col4<TA>(A + (size_t)min(jj + u * GV_WAVES, j1 - 1) * lda, rA, rB, vA, vB, vec, vv[u]);
+    for (int u = 0; u < UNR; ++u)
+      load_col4<TA, ALLVEC>(A + (size_t)min(jj + u * GV_WAVES, j1 - 1) * lda, rA, rB, vA, vB, vec, vv[u]);
   };
   if (vA > 0) load_batch(va, j);
   // 3. slice into LDS
@@ -217,7 +240,6 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   __syncthreads();
   // 4. batches of UNR columns per wave.  Loads are unconditional (column index clamped;
   // past-the-slice and outside-the-triangle columns contribute exact zeros).
-  double h[4] = {0, 0, 0, 0}, l[4] = {0, 0, 0, 0}, f[4] = {0, 0, 0, 0};
   auto use_batch = [&](const TA (&vv)[UNR][4], int jj) {
 #pragma unroll
     for (int u = 0; u < UNR; ++u) {
@@ -266,6 +288,9 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
       }
     }
   }
+  };
+  if (aligned && rlo + GV_ROWS <= n) body(std::true_type{});
+  else body(std::false_type{});
   // fold the waves' sums in wave order (LDS reused: wait until every wave is done with sx)
   __syncthreads();
   double* sh = lds;
