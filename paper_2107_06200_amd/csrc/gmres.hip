@@ -163,13 +163,16 @@ orthogonal:
     double* hc = lds_col ? sHc : H + (size_t)j * ldh;
     const double* cc = lds_col ? sCs : cs;
     const double* ss = lds_col ? sSn : sn;
-    hc[j + 1] = hn;
+    // the entry carried from one rotation to the next stays in a register (the same
+    // operations as rotating the stored column in place, without a store-to-load
+    // round trip per rotation)
+    double a = hc[0];
     for (int i = 0; i < j; ++i) {
-      const double a = hc[i], b = hc[i + 1];
-      hc[i] = __dadd_rn(__dmul_rn(cc[i], a), __dmul_rn(ss[i], b));
-      hc[i + 1] = __dadd_rn(__dmul_rn(-ss[i], a), __dmul_rn(cc[i], b));
+      const double b = hc[i + 1], ci = cc[i], si = ss[i];
+      hc[i] = __dadd_rn(__dmul_rn(ci, a), __dmul_rn(si, b));
+      a = __dadd_rn(__dmul_rn(-si, a), __dmul_rn(ci, b));
     }
-    const double a = hc[j], b = hc[j + 1];
+    const double b = hn;
     const double r = hypot(a, b);
     double c = 1.0, s = 0.0;
     if (r != 0.0) { c = a / r; s = b / r; }
