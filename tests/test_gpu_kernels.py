@@ -372,6 +372,22 @@ def test_getrs_multiblock_vs_oracle(M, h, fmt, comp, n):
         assert np.abs(got - want).max() <= 64 * F.u(comp) * np.abs(want).max()
 
 
+def test_getrs_more_workgroups_than_resident(M, h):
+    """fp64 factors: the substitution launch (one chain and one helper per block and
+    sweep, 2 nblk + 1 = 257 workgroups for n = 8150) needs more workgroups than the
+    GPU holds at once (the fp64 tiles take most of a compute unit's LDS: one workgroup
+    per compute unit), so a helper starts as another finishes; the solve must still
+    complete and agree with the oracle."""
+    n = 8150
+    W, piv = multiblock_factors(n, "fp64", 77)
+    t = np.random.default_rng(78).standard_normal(n)
+    want = OSV.lu_solve(W, piv, t, "fp64")
+    Wd = to_dev_fmt(W, "fp64", M)
+    ip = torch.from_numpy(piv.astype(np.int32)).to(DEV)
+    got = M.getrs(h, Wd, "fp64", ip, tdev(t), "fp64").cpu().numpy()
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-11 * np.abs(want).max())
+
+
 @pytest.mark.parametrize("n", [300, 449])
 def test_getrs_dd_multiblock_vs_oracle(M, h, n):
     W, piv = multiblock_factors(n, "fp64", 41 + n)
