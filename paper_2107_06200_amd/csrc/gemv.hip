@@ -87,6 +87,30 @@ __device__ __forceinline__ void load_col4(const TA* __restrict__ pc, int rA, int
   }
 }
 
+// Triangular operands, workgroups whose rows lie inside the matrix: one column's
+// entries through a buffer descriptor covering that column (nbytes), so that a lane
+// whose row group does not need the column (outside the triangle, or past the slice)
+// passes an out-of-range offset and reads zeros without fetching anything.
+template <typename TA>
+__device__ __forceinline__ void load_col4_tri(const TA* __restrict__ pc, int nbytes, int rA, int rB, bool need0,
+                                              bool need1, TA v[4]) {
+  typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+  typedef float f32x4 __attribute__((ext_vector_type(4)));
+  typedef double f64x2 __attribute__((ext_vector_type(2)));
+  constexpr int OOB = 0x7ffffff0;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc((void*)pc, (short)0, nbytes, 0x00020000);
+  // whole-vector bit casts (a bit cast of a single vector element lets the compiler
+  // narrow the 16-byte load to its first dword)
+  if constexpr (sizeof(TA) == 4) {
+    const f32x4 f = __builtin_bit_cast(f32x4, (u32x4)__builtin_amdgcn_raw_buffer_load_b128(rs, need0 ? rA * 4 : OOB, 0, 0));
+    v[0] = f.x; v[1] = f.y; v[2] = f.z; v[3] = f.w;
+  } else {
+    const f64x2 d0 = __builtin_bit_cast(f64x2, (u32x4)__builtin_amdgcn_raw_buffer_load_b128(rs, need0 ? rA * 8 : OOB, 0, 0));
+    const f64x2 d1 = __builtin_bit_cast(f64x2, (u32x4)__builtin_amdgcn_raw_buffer_load_b128(rs, need1 ? rB * 8 : OOB, 0, 0));
+    v[0] = d0.x; v[1] = d0.y; v[2] = d1.x; v[3] = d1.y;
+  }
+}
+
 // Does a row group [rmin, rmax] need column j of a TRI-triangular operand?
 template <int TRI>
 __device__ __forceinline__ bool needs(int j, int rmin, int rmax) {
@@ -217,8 +241,17 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   int j = j0 + w;
   auto load_batch = [&](TA (&vv)[UNR][4], int jj) {
 #pragma unroll
-    for (int u = 0; u < UNR; ++u)
-      load_col4<TA, ALLVEC>(A + (size_t)min(jj + u * GV_WAVES, j1 - 1) * lda, rA, rB, vA, vB, vec, vv[u]);
+    for (int u = 0; u < UNR; ++u) {
+      const int col = jj + u * GV_WAVES;
+      const TA* pc = A + (size_t)min(col, j1 - 1) * lda;
+      if constexpr (ALLVEC && TRI != 0) {
+        const bool in_slice = col < j1;
+        load_col4_tri<TA>(pc, n * (int)sizeof(TA), rA, rB, in_slice && needs<TRI>(col, gmin0, gmax0),
+                          in_slice && needs<TRI>(col, gmin1, gmax1), vv[u]);
+      } else {
+        load_col4<TA, ALLVEC>(pc, rA, rB, vA, vB, vec, vv[u]);
+      }
+    }
   };
   if (vA > 0) load_batch(va, j);
   // 3. slice into LDS
