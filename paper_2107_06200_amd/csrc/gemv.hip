@@ -437,14 +437,14 @@ GemvPlan gemv_plan(int n, int tri, int a_prec, int mode) {
 }
 
 // Waves per workgroup, and double buffering, per configuration (measured on n = 4096):
-// float32 full products use 16 waves of eight columns in flight; float32 triangles 8
-// waves, double-buffered (the compact grid keeps every busy pair resident); float64
-// float64-accumulated products 8 waves (two batches of float64 columns need the
-// register budget of a 512-thread workgroup); double-double modes 16 waves.
+// float32 full products use 16 waves of eight columns in flight; triangles 8 waves,
+// double-buffered (the compact grid keeps every busy pair resident; float64 triangles
+// four columns per batch, eight measured slower); float64 float64-accumulated full
+// products 8 waves of eight columns; double-double modes 16 waves.
 static constexpr int gemv_waves(bool fp32, int mode, int tri) {
   return mode != 0 ? 16 : (fp32 && tri == 0 ? 16 : 8);
 }
-static constexpr bool gemv_dbuf(bool fp32, int mode, int tri) { return fp32 && mode == 0 && tri != 0; }
+static constexpr bool gemv_dbuf(bool fp32, int mode, int tri) { return mode == 0 && tri != 0; }
 static int gemv_step(bool fp32, int mode, int tri) {
   const int unr = (fp32 || (mode == 0 && tri == 0)) ? 8 : 4;   // UNR of k_gemv
   return unr * gemv_waves(fp32, mode, tri);
