@@ -237,7 +237,7 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   // the matrix (aligned), with branch-free 16-byte loads, and for the rest.
   auto body = [&](auto allvec_tag) {
   constexpr bool ALLVEC = decltype(allvec_tag)::value;
-  TA va[UNR][4];
+  TA va[UNR][4], vb[UNR][4];   // vb: second buffer of the double-buffered variant
   int j = j0 + w;
   auto load_batch = [&](TA (&vv)[UNR][4], int jj) {
 #pragma unroll
@@ -253,7 +253,10 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
       }
     }
   };
-  if (vA > 0) load_batch(va, j);
+  if (vA > 0) {
+    load_batch(va, j);
+    if constexpr (DB) load_batch(vb, j + STEP);   // both buffers in flight during the staging
+  }
   // 3. slice into LDS
   if (!in.xpart) {
 #pragma unroll
@@ -289,15 +292,14 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
   };
   if (vA > 0) {
     if constexpr (DB) {
-      // double-buffered: the next batch's loads are issued before the current one is
-      // consumed; the first NBU batches are straight-line code so that every wait on a
-      // batch leaves the following batch in flight
+      // double-buffered: va holds batch j and vb batch j + STEP (both issued before the
+      // staging); each buffer is refilled right after it is consumed.  The first NBU
+      // batches are straight-line code so that every wait on a batch leaves the
+      // following batch in flight.
       constexpr int NBU = 16;
-      TA vb[UNR][4];
       bool more = true;
 #pragma unroll
       for (int bt = 0; bt < NBU; bt += 2) {
-        load_batch(vb, j + STEP);
         use_batch(va, j);
         j += STEP;
         if (j >= j1) { more = false; break; }
@@ -305,12 +307,17 @@ __global__ __launch_bounds__(64 * WV) void k_gemv(int n, const TA* __restrict__ 
         use_batch(vb, j);
         j += STEP;
         if (j >= j1) { more = false; break; }
+        load_batch(vb, j + STEP);
       }
-      while (more) {   // slices wider than NBU batches: the rest single-buffered (va is loaded)
+      while (more) {   // slices wider than NBU batches: the same pattern, rolled
         use_batch(va, j);
         j += STEP;
         if (j >= j1) break;
-        load_batch(va, j);
+        load_batch(va, j + STEP);
+        use_batch(vb, j);
+        j += STEP;
+        if (j >= j1) break;
+        load_batch(vb, j + STEP);
       }
     } else {
       for (;;) {
