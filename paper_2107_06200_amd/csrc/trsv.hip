@@ -54,6 +54,7 @@ struct TrsvK {
   unsigned long long* mpf;   // forward helper sums
   unsigned long long* mpb;   // backward helper sums
   unsigned long long* mrf;   // forward right-hand sides published by the helpers
+  int vecld;                 // W and its column stride are 16-byte aligned (vector tile loads)
 };
 
 // Broadcast lane `lane`'s value to the wave through scalar registers (lane uniform).
@@ -248,6 +249,53 @@ __device__ __forceinline__ void tile_st(int n, int r0, int c0, int wv, int lane,
   }
 }
 
+// The same tile by 16-byte loads (full blocks of an aligned W; not for float64 factors):
+// a load covers EPL consecutive rows of one column, a wave instruction 64 / (64 / EPL)
+// = EPL columns.  Instruction ci of the tile (ci = wv + NWV it) covers columns
+// EPL ci .. EPL ci + EPL - 1; lane l takes column EPL ci + l / (64 / EPL), rows
+// EPL (l % (64 / EPL)) ...
+template <int P>
+constexpr int tile_epl() {
+  return 16 / (int)sizeof(typename Store<P>::T);
+}
+template <int P, int NWV>
+constexpr int tile_itv() {
+  return (TB / tile_epl<P>() + NWV - 1) / NWV;
+}
+
+template <int P, int NWV>
+__device__ __forceinline__ void tile_ldv(const typename Store<P>::T* __restrict__ W, int ldw, int r0, int c0, int wv,
+                                         int lane, uint4 (&v)[tile_itv<P, NWV>()]) {
+  constexpr int EPL = tile_epl<P>(), LPC = 64 / EPL, NI = TB / EPL;
+#pragma unroll
+  for (int it = 0; it < tile_itv<P, NWV>(); ++it) {
+    const int ci = min(wv + NWV * it, NI - 1);
+    const int k = EPL * ci + lane / LPC;
+    v[it] = *reinterpret_cast<const uint4*>(W + (size_t)(c0 + k) * ldw + r0 + EPL * (lane % LPC));
+  }
+}
+
+template <int P, int NWV, int MODE, typename LT>
+__device__ __forceinline__ void tile_stv(int wv, int lane, const uint4 (&v)[tile_itv<P, NWV>()], LT (*sT)[TB + 1]) {
+  typedef typename Store<P>::T ST;
+  constexpr int EPL = tile_epl<P>(), LPC = 64 / EPL, NI = TB / EPL;
+#pragma unroll
+  for (int it = 0; it < tile_itv<P, NWV>(); ++it) {
+    const int ci = wv + NWV * it;
+    if (ci < NI) {
+      const int k = EPL * ci + lane / LPC;
+      ST e[EPL];
+      __builtin_memcpy(e, &v[it], sizeof(e));
+#pragma unroll
+      for (int q = 0; q < EPL; ++q) {
+        const int i = EPL * (lane % LPC) + q;
+        const bool ok = MODE == 0 || (MODE == 1 ? (i > k) : (i < k));
+        sT[i][k] = ok ? (LT)Store<P>::to_d(e[q]) : (LT)0;
+      }
+    }
+  }
+}
+
 template <typename LT>
 struct ChainLds {
   LT D[2][TB][TB + 1];   // diagonal tiles (strict triangle)
@@ -412,12 +460,30 @@ __device__ __forceinline__ void chain_sweep(const TrsvK& a, ChainLds<LT>& L) {
     // next block's products with the LAG - 2 blocks before the current one, then the
     // loads for the following step
     const int w = gu - 1;
+    constexpr bool VT = P != P_FP64;   // vector tile loads available
+    constexpr int NV = VT ? tile_itv<P, 3>() : 1;
     ST t1[tile_it<TNT - 64>()], t2[tile_it<TNT - 64>()];
+    uint4 u1[NV], u2[NV];
     ST pr[LAG - 2][NCOL3];
+    // full 64 x 64 blocks of an aligned W take the 16-byte loads (fewer load
+    // instructions than a wave may have in flight)
+    auto vec_ok = [&](int bn, int b2) {
+      return VT && a.vecld && bn >= 0 && bn * TB + TB <= n && b2 >= 0 && b2 * TB + TB <= n;
+    };
     auto issue_loads = [&](int blk) {   // for the step that solves block blk
       const int bn = nxt(blk, 1), b2 = nxt(blk, 2);
-      tile_ld<P, TNT - 64>(W, ldw, n, bn * TB, bn * TB, w, lr, t1);
-      tile_ld<P, TNT - 64>(W, ldw, n, b2 * TB, bn * TB, w, lr, t2);
+      if constexpr (VT) {
+        if (vec_ok(bn, b2)) {
+          tile_ldv<P, 3>(W, ldw, bn * TB, bn * TB, w, lr, u1);
+          tile_ldv<P, 3>(W, ldw, b2 * TB, bn * TB, w, lr, u2);
+        } else {
+          tile_ld<P, TNT - 64>(W, ldw, n, bn * TB, bn * TB, w, lr, t1);
+          tile_ld<P, TNT - 64>(W, ldw, n, b2 * TB, bn * TB, w, lr, t2);
+        }
+      } else {
+        tile_ld<P, TNT - 64>(W, ldw, n, bn * TB, bn * TB, w, lr, t1);
+        tile_ld<P, TNT - 64>(W, ldw, n, b2 * TB, bn * TB, w, lr, t2);
+      }
 #pragma unroll
       for (int d = 0; d < LAG - 2; ++d)
         load_raw<P, NCOL3, 3>(W, ldw, n, bn * TB + lr, nxt(blk, -1 - d) * TB + w, pr[d]);
@@ -429,8 +495,18 @@ __device__ __forceinline__ void chain_sweep(const TrsvK& a, ChainLds<LT>& L) {
       const int bn = nxt(blk, 1), b2 = nxt(blk, 2);
       const bool has_next = s + 1 < nblk;
       if (has_next) {
-        tile_st<P, TNT - 64, FWD ? 1 : 2>(n, bn * TB, bn * TB, w, lr, t1, L.D[buf ^ 1]);
-        if (b2 >= 0 && b2 < nblk) tile_st<P, TNT - 64, 0>(n, b2 * TB, bn * TB, w, lr, t2, L.B[buf ^ 1]);
+        bool done = false;
+        if constexpr (VT) {
+          if (vec_ok(bn, b2)) {
+            tile_stv<P, 3, FWD ? 1 : 2>(w, lr, u1, L.D[buf ^ 1]);
+            tile_stv<P, 3, 0>(w, lr, u2, L.B[buf ^ 1]);
+            done = true;
+          }
+        }
+        if (!done) {
+          tile_st<P, TNT - 64, FWD ? 1 : 2>(n, bn * TB, bn * TB, w, lr, t1, L.D[buf ^ 1]);
+          if (b2 >= 0 && b2 < nblk) tile_st<P, TNT - 64, 0>(n, b2 * TB, bn * TB, w, lr, t2, L.B[buf ^ 1]);
+        }
       }
       double ph = 0.0, pl = 0.0;
       if (has_next) {
@@ -579,6 +655,10 @@ int trsv(Ctx& c, const TrsvArgs& a) {
   k.mpf = mbf + 4 * (size_t)n;
   k.mrf = mbf + 8 * (size_t)n;
   k.mpb = mbb + 4 * (size_t)n;
+  {
+    const size_t es = a.prec == P_FP64 ? 8 : a.prec == P_FP32 ? 4 : 2;
+    k.vecld = ((uintptr_t)a.W % 16 == 0) && (((size_t)a.ldw * es) % 16 == 0);
+  }
   switch (a.prec) {
     case P_FP16: launch_trsv<P_FP16>(c, k, grid, a.comp); break;
     case P_BF16: launch_trsv<P_BF16>(c, k, grid, a.comp); break;
