@@ -292,13 +292,15 @@ def oracle_factors(n, fmt, nb, seed, scaled=False):
     return A, W, piv, scal
 
 
-@pytest.mark.parametrize("fmt,comp", [("fp16", "fp16"), ("bf16", "bf16"), ("fp16", "fp32"), ("fp16", "fp64"),
-                                      ("fp32", "fp32"), ("fp32", "fp64"), ("fp64", "fp64")])
+# (factor format, solution format, two-sided scaling): the scaling applies to fp16 factors only
+_GETRS_CASES = [("fp16", "fp16", False), ("bf16", "bf16", False), ("fp16", "fp32", False), ("fp16", "fp64", False),
+                ("fp32", "fp32", False), ("fp32", "fp64", False), ("fp64", "fp64", False),
+                ("fp16", "fp16", True), ("fp16", "fp32", True), ("fp16", "fp64", True)]
+
+
+@pytest.mark.parametrize("fmt,comp,scaled", _GETRS_CASES)
 @pytest.mark.parametrize("n", [1, 64, 150])
-@pytest.mark.parametrize("scaled", [False, True])
 def test_getrs_vs_oracle(M, h, fmt, comp, n, scaled):
-    if scaled and fmt != "fp16":
-        pytest.skip("scaling is defined for fp16 factors")
     A, W, piv, scal = oracle_factors(n, fmt, 16, 11 + n, scaled)
     t = np.random.default_rng(5).standard_normal(n)
     want = OSV.lu_solve(W, piv, t, comp, scal)
