@@ -102,9 +102,12 @@ __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict
                                                  int ldv, const double* __restrict__ w_in, double* __restrict__ H, int ldh,
                                                  double* __restrict__ cs, double* __restrict__ sn,
                                                  double* __restrict__ g, const double* __restrict__ beta0, double tau,
-                                                 GStatus* st) {
+                                                 GStatus* st, GStatus* mirror) {
   static_assert(NT == 512 || NT == 1024, "8 or 16 wave partials");
-  if (st->done) return;
+  if (st->done) {
+    if (mirror && threadIdx.x == 0) mirror->done = 1;
+    return;
+  }
   // per-wave partial sums, double-buffered by the parity of the inner-product index
   // so that one barrier per inner product suffices
   __shared__ double sh[2][NT / 64];
@@ -185,6 +188,10 @@ orthogonal:
     const bool stop = !__builtin_isfinite(g[j + 1]) || e <= tau * b0 || hn == 0.0;
     st->jcount = j + 1;
     st->done = stop ? 1 : 0;
+    if (mirror) {
+      mirror->jcount = j + 1;
+      mirror->done = stop ? 1 : 0;
+    }
   }
   if (lds_col) {
     __syncthreads();
@@ -204,38 +211,41 @@ orthogonal:
 
 template <int G, int D, int NT, bool TAIL>
 static void launch_arnoldi_t(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
-                             double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
+                             double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st,
+                             GStatus* mirror) {
   switch (u) {
     case P_FP16:
-      k_arnoldi<G, P_FP16, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st);
+      k_arnoldi<G, P_FP16, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
       break;
     case P_BF16:
-      k_arnoldi<G, P_BF16, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st);
+      k_arnoldi<G, P_BF16, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
       break;
     case P_FP32:
-      k_arnoldi<G, P_FP32, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st);
+      k_arnoldi<G, P_FP32, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
       break;
     default:
-      k_arnoldi<G, P_FP64, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st);
+      k_arnoldi<G, P_FP64, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
       break;
   }
 }
 
 template <int G, int D, int NT>
 static void launch_arnoldi_g(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
-                             double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
-  if (n == G * NT) launch_arnoldi_t<G, D, NT, false>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else launch_arnoldi_t<G, D, NT, true>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+                             double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st,
+                             GStatus* mirror) {
+  if (n == G * NT) launch_arnoldi_t<G, D, NT, false>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else launch_arnoldi_t<G, D, NT, true>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
 }
 
 // values per thread G, basis vectors in flight D, threads NT (see above)
 static void launch_arnoldi(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
-                           double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st) {
-  if (n <= 512) launch_arnoldi_g<1, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else if (n <= 1024) launch_arnoldi_g<2, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else if (n <= 2048) launch_arnoldi_g<4, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else if (n <= 4096) launch_arnoldi_g<8, 4, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
-  else launch_arnoldi_g<8, 2, 1024>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st);
+                           double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st,
+                             GStatus* mirror) {
+  if (n <= 512) launch_arnoldi_g<1, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else if (n <= 1024) launch_arnoldi_g<2, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else if (n <= 2048) launch_arnoldi_g<4, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else if (n <= 4096) launch_arnoldi_g<8, 4, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else launch_arnoldi_g<8, 2, 1024>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
 }
 
 // y = R^{-1} g (upper triangular from the rotated Hessenberg), one wave,
@@ -315,24 +325,39 @@ int gmres(Ctx& c, GmresWork& gw, const GmresOp& op, const double* rhat, double t
     HIP_CHECK(hipGetLastError());
     first = false;
     int jdone = 0;
-    // the host reads the status after 8, 16, 32, ... iterations and at the end of the
-    // cycle; launches after convergence are no-ops on the device, so at most as many
-    // iterations are skipped as have run, while a long cycle costs few host round trips
+    // the host checks the status after 8, 16, 32, ... iterations and reads it at the end
+    // of the cycle; launches after convergence are no-ops on the device, so at most as
+    // many iterations are skipped as have run.  At a check iteration the Arnoldi launch
+    // also writes the status to a pinned host mirror, and the host waits for the event
+    // behind that launch only after two more iterations are queued: the device never
+    // runs dry at a check (the answer arrives two iterations late, which costs at most
+    // two no-op iterations)
     int next_check = 8;
+    int wait_at = -1;     // iteration after whose launch the pending check is read
     bool fresh = false;   // host_status read after the last launch
     for (int it = 0; it < m; ++it) {
       fresh = false;
       rc = op.apply_full(c, gw.V + (size_t)it * ldv, gw.w, &st->done);
       if (rc) return rc;
+      const bool check = it + 1 == next_check && it + 1 < m && wait_at < 0;
+      if (it + 1 == next_check) next_check *= 2;
+      if (check) *(volatile int*)&gw.host_mirror->done = 0;   // no launch writes it now
       MSIR_TIMED(c, MSIR_T_ARNOLDI, launch_arnoldi(c.stream, n, it, gw.V, gw.Vf, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g,
-                                                   gw.beta0, tau, u, st));
+                                                   gw.beta0, tau, u, st, check ? gw.dev_mirror : nullptr));
       HIP_CHECK(hipGetLastError());
-      if (it + 1 == next_check || it + 1 == m) {
-        next_check *= 2;
+      if (check) {
+        HIP_CHECK(hipEventRecord(gw.ev_mirror, c.stream));
+        wait_at = it + 2;
+      }
+      if (it + 1 == m) {
         HIP_CHECK(hipMemcpyAsync(gw.host_status, st, sizeof(GStatus), hipMemcpyDeviceToHost, c.stream));
         HIP_CHECK(hipStreamSynchronize(c.stream));
         fresh = true;
-        if (gw.host_status->done) break;
+        wait_at = -1;
+      } else if (it == wait_at) {
+        HIP_CHECK(hipEventSynchronize(gw.ev_mirror));
+        wait_at = -1;
+        if (*(volatile int*)&gw.host_mirror->done) break;
       }
     }
     if (!fresh) {

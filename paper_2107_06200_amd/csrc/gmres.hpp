@@ -18,6 +18,11 @@ struct GmresWork {
   float* Vf = nullptr;   // float32 copy of the basis (working formats below float64)
   GStatus* status = nullptr;
   GStatus* host_status = nullptr;
+  // status mirror in pinned host memory, written by the Arnoldi launch at a check
+  // iteration; the host reads it after an event recorded behind that launch
+  GStatus* host_mirror = nullptr;
+  GStatus* dev_mirror = nullptr;
+  hipEvent_t ev_mirror = nullptr;
   DevBuf buf;
   int ensure(Ctx& c, int n, int m);
   void free_all(Ctx& c);

@@ -150,6 +150,14 @@ int GmresWork::ensure(Ctx& c, int n, int m) {
   if (!host_status) {
     if (hipHostMalloc((void**)&host_status, sizeof(GStatus)) != hipSuccess) return MSIR_ERR_HIP;
   }
+  if (!host_mirror) {
+    if (hipHostMalloc((void**)&host_mirror, sizeof(GStatus)) != hipSuccess) return MSIR_ERR_HIP;
+    memset(host_mirror, 0, sizeof(GStatus));
+    if (hipHostGetDevicePointer((void**)&dev_mirror, host_mirror, 0) != hipSuccess) return MSIR_ERR_HIP;
+  }
+  if (!ev_mirror) {
+    if (hipEventCreateWithFlags(&ev_mirror, hipEventDisableTiming) != hipSuccess) return MSIR_ERR_HIP;
+  }
   return 0;
 }
 
@@ -159,6 +167,11 @@ void GmresWork::free_all(Ctx& c) {
   buf.bytes = 0;
   if (host_status) (void)hipHostFree(host_status);
   host_status = nullptr;
+  if (host_mirror) (void)hipHostFree(host_mirror);
+  host_mirror = nullptr;
+  dev_mirror = nullptr;
+  if (ev_mirror) (void)hipEventDestroy(ev_mirror);
+  ev_mirror = nullptr;
   V = nullptr;
   Vf = nullptr;
   ncap = mcap = 0;
