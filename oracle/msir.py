@@ -15,8 +15,9 @@ Sec. 2.1.1 and the scalings of Sec. 2.1.2:
 
 Readings used where the paper is silent or inconsistent (each listed with its
 reason in the design notes of the repository):
-  * x is stored in its own precision u_x (default fp64; u_x = u reproduces
-    Alg. 4 literally).  The thresholds z <= u and phi <= sqrt(n) u use u_x.
+  * x is stored in its own precision u_x (default fp64).  u_x = u reproduces
+    Alg. 4 literally: x is stored in u, also after an escalation lowers u, so u_x
+    then follows u.  The thresholds z <= u and phi <= sqrt(n) u use u_x.
   * monitors use the true correction delta = ||r||_inf ||d||_inf.
   * the iteration criterion is iter >= i_max; the GMRES criterion k >= k_max
     with GMRES capped at ceil(k_max) iterations.
@@ -179,6 +180,7 @@ def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None):
     P = params
     uf, u, ur, ux = P.uf, P.u, P.ur, P.ux
     u0 = u
+    ux_follows_u = P.ux == P.u          # Alg. 4 stores x in u
     k_max = 0.1 * n if P.k_max is None else P.k_max
     normA = float(np.abs(A).sum(axis=1).max())
     normb = float(np.abs(b).max())
@@ -325,6 +327,8 @@ def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None):
                 uf = nuf
                 if F.u(uf) < F.u(u):
                     u = uf
+                if ux_follows_u:
+                    ux = u                  # x keeps its values; later roundings use the new u
                 if F.u(ur) > F.u(u) ** 2:
                     ur = square(u)
                 level += 1
