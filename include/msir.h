@@ -68,7 +68,8 @@ typedef enum { MSIR_SCALE_NEVER = 0, MSIR_SCALE_AUTO = 1, MSIR_SCALE_ALWAYS = 2,
  * design notes.  Fill with msir_params_default() and override.                 */
 typedef struct {
     msir_prec uf, u, ur;   /* initial (u_f, u, u_r); u in {FP32, FP64}; ur in {FP64, DD} */
-    msir_prec ux;          /* storage precision of x: FP64 (default) or = u (paper mode) */
+    msir_prec ux;          /* storage precision of x: FP64 (default) or = u (paper mode:
+                              x is stored in u, also after an escalation lowers u)     */
     int    i_max;          /* maximum refinement steps of each variant (>= 1)           */
     double tau;            /* GMRES relative preconditioned residual tolerance (> 0);
                               <= 0 selects 1e-6 for u = fp32 and 1e-10 for u = fp64   */
@@ -79,7 +80,9 @@ typedef struct {
     msir_conv conv;        /* convergence detection mode                              */
     double tol_nbe;        /* tolerance of MSIR_CONV_BACKWARD and _COMPONENTWISE      */
     msir_scale scaling;    /* Sec. 2.1.2 scaling policy                               */
-    int    nb;             /* LU panel width; 0 = automatic (see msir_nb_auto)        */
+    int    nb;             /* LU panel width; 0 = automatic (see msir_nb_auto).  An
+                              explicit width must suit every factor format the
+                              escalation ladder can reach from uf (else -8)         */
     int    max_steps;      /* global cap on refinement steps (safety)                 */
     int    lu_update;      /* trailing update of fp16/bf16/fp32 factors: MSIR_LU_MFMA
                               (matrix cores, default) or MSIR_LU_FMA (sequential fp32
@@ -115,7 +118,7 @@ typedef struct {
     int    cged;            /* Alg. 4 output flag                                */
     int    status;          /* same code as the return value                     */
     int    steps;           /* refinement steps performed (history length)       */
-    int    n_lu;            /* factorizations performed                          */
+    int    n_lu;            /* factorizations performed by this solve            */
     int    gmres_iters;     /* total GMRES iterations                            */
     int    final_uf, final_u, final_ur;
     double nbe;             /* final normwise backward error, residual in dd     */
@@ -194,14 +197,24 @@ MSIR_API int msir_gmres_ir5(msir_handle* h, int n, const double* dA, int lda, co
                    const double* dx_true, const msir_params* params, msir_prec ug, msir_prec up,
                    msir_result* out, msir_step* hist, int hist_cap, int* hist_len);
 
-/* nrhs right-hand sides sharing one factorization per precision level (the
- * multi-RHS reading of Alg. 4: an independent controller per column; when a
- * column escalates, the higher-precision factorization is computed once and
- * reused by every column that reaches it).  dB, dX: n x nrhs column-major.
- * outs: NULL or nrhs results.  Returns the worst status over the columns.      */
+/* nrhs right-hand sides of one A (Alg. 4 with several right-hand sides): an
+ * independent controller per column (its own stages, triggers and escalations),
+ * over a factor cache with one slot per factor format.  A level (u_f) is factored
+ * by the first column that reaches it, together with the explicit inverses its
+ * GMRES operator needs, and reused by every later column that reaches it; A's fp32
+ * copy likewise.  Columns run one after another on the handle's stream.
+ * dB, dX: n x nrhs column-major (ldb, ldx >= n).  dXt: NULL or the exact solutions
+ * (ldxt >= n; enables ferr and CONV_TRUE).  outs: NULL or nrhs results; outs[j].n_lu
+ * counts the factorizations performed while column j ran (0 when every level it
+ * used was already cached), so their sum is the number of distinct levels reached.
+ * hist: NULL or a host array of nrhs * hist_cap steps, column j's history from
+ * hist + j * hist_cap; hist_len: NULL or nrhs counts (each may exceed hist_cap).
+ * Returns the worst status over the columns, or an error (< 0): -10 CONV_TRUE
+ * without dXt, -12 invalid params (as msir_solve's -8), -15 hist_cap < 0.        */
 MSIR_API int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda,
-                     const double* dB, int ldb, double* dX, int ldx,
-                     const msir_params* params, msir_result* outs);
+                     const double* dB, int ldb, double* dX, int ldx, const double* dXt, int ldxt,
+                     const msir_params* params, msir_result* outs, msir_step* hist, int hist_cap,
+                     int* hist_len);
 
 /* Independent systems of uneven sizes solved with one handle: system i has order
  * n[i], matrix dA[i] (lda[i]), right-hand side db[i] and solution dx[i].  Host

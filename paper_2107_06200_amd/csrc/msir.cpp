@@ -257,20 +257,42 @@ struct FactorState {
   size_t vec_bytes = 0;
 };
 
+// One factorization and the explicit inverses of its factors.
+struct FactorSlot {
+  FactorState f;
+  DevBuf Xd, Yd, Xf, Yf;
+  bool inv64 = false, inv32 = false;  // inverses of this factorization are valid
+  bool valid = false;                 // f holds the factorization of the cached A
+};
+
+// Slots 0..3 cache one factorization per factor format (msir_solve_multi: every
+// column's controller reuses the factorization of a level once one column reached it);
+// a single solve keeps its levels in slot 0; slot 4 holds caller-supplied factors for
+// the step entry points (its W is not owned).
+constexpr int kExtSlot = 4;
+
 struct msir_handle {
   Ctx c;
   GmresWork gw;
-  FactorState f;
-  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Xd, Yd, Xf, Yf, Acsr;
-  bool inv64 = false, inv32 = false;  // inverses of the current factorization are valid
+  FactorSlot slot[5];
+  FactorSlot* cur = &slot[0];
+  bool share = false;            // reuse valid slots instead of refactoring
+  int factorizations = 0;        // factorizations performed (counter for the results)
+  bool au_valid = false;         // Au holds fl32(A) of the cached A (share mode)
+  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Acsr;
   double* dev_small = nullptr;   // device scalars
   double* host_small = nullptr;  // pinned host scalars
   std::vector<int> hpiv, hperm, hpinv;
   hipEvent_t ev[4];
 };
 
+static void invalidate_factors(msir_handle* h) {
+  for (FactorSlot& s : h->slot) s.valid = s.inv64 = s.inv32 = false;
+  h->au_valid = false;
+}
+
 static int ensure_factor(msir_handle* h, int n, int prec) {
-  FactorState& f = h->f;
+  FactorState& f = h->cur->f;
   const size_t wb = (size_t)n * n * store_bytes(prec);
   if (f.Wbytes < wb) {
     if (f.W) { (void)hipStreamSynchronize(h->c.stream); h->c.release(f.W, f.Wbytes); f.W = nullptr; f.Wbytes = 0; }
@@ -305,13 +327,17 @@ static int sync_read(msir_handle* h, const double* dev, int count) {
   return 0;
 }
 
-// Factor A in u_f = prec with the Sec. 2.1.2 policy.  Leaves factors in h->f.
+// Factor A in u_f = prec with the Sec. 2.1.2 policy.  Leaves the factors in the slot
+// of that level (h->cur).  In share mode a valid slot is reused as it is.
 static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, int scaling_mode, int nb,
                      int update) {
+  h->cur = &h->slot[h->share ? prec : 0];
+  if (h->share && h->cur->valid && h->cur->f.prec == prec && h->cur->f.n == n) return 0;
+  h->cur->valid = false;
   int rc = ensure_factor(h, n, prec);
   if (rc) return rc;
-  h->inv64 = h->inv32 = false;
-  FactorState& f = h->f;
+  h->cur->inv64 = h->cur->inv32 = false;
+  FactorState& f = h->cur->f;
   Ctx& c = h->c;
   double* dmu = h->dev_small + 8;
   double* dtmp = vbuf(h, h->tmp_lo, n);
@@ -372,45 +398,63 @@ static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, 
   rc = diag_reciprocals(c, n, prec, f.W, n, f.rinv);
   if (rc) return rc;
   HIP_CHECK(hipStreamSynchronize(c.stream));
+  h->cur->valid = true;
+  h->factorizations += 1;
   return 0;
 }
 
 // Inverses of the current factors in the operator precision p (FP32 or FP64).
 static int ensure_inverses(msir_handle* h, int n, int p, const void** X, const void** Y) {
   Ctx& c = h->c;
-  if (!h->inv64) {
-    double* Xd = (double*)c.grow(h->Xd, (size_t)n * n * sizeof(double));
-    double* Yd = (double*)c.grow(h->Yd, (size_t)n * n * sizeof(double));
+  FactorSlot& s = *h->cur;
+  if (!s.inv64) {
+    double* Xd = (double*)c.grow(s.Xd, (size_t)n * n * sizeof(double));
+    double* Yd = (double*)c.grow(s.Yd, (size_t)n * n * sizeof(double));
     if (!Xd || !Yd) return MSIR_ERR_ALLOC;
-    int rc = tri_inverses(c, n, h->f.prec, h->f.W, n, Xd, Yd);
+    int rc = tri_inverses(c, n, s.f.prec, s.f.W, n, Xd, Yd);
     if (rc) return rc;
-    h->inv64 = true;
-    h->inv32 = false;
+    s.inv64 = true;
+    s.inv32 = false;
   }
   if (p == P_FP64) {
-    *X = h->Xd.p;
-    *Y = h->Yd.p;
+    *X = s.Xd.p;
+    *Y = s.Yd.p;
     return 0;
   }
-  if (!h->inv32) {
-    float* Xf = (float*)c.grow(h->Xf, (size_t)n * n * sizeof(float));
-    float* Yf = (float*)c.grow(h->Yf, (size_t)n * n * sizeof(float));
+  if (!s.inv32) {
+    float* Xf = (float*)c.grow(s.Xf, (size_t)n * n * sizeof(float));
+    float* Yf = (float*)c.grow(s.Yf, (size_t)n * n * sizeof(float));
     if (!Xf || !Yf) return MSIR_ERR_ALLOC;
-    int rc = square_to_f32(c, n, (const double*)h->Xd.p, Xf);
+    int rc = square_to_f32(c, n, (const double*)s.Xd.p, Xf);
     if (rc) return rc;
-    rc = square_to_f32(c, n, (const double*)h->Yd.p, Yf);
+    rc = square_to_f32(c, n, (const double*)s.Yd.p, Yf);
     if (rc) return rc;
-    h->inv32 = true;
+    s.inv32 = true;
   }
-  *X = h->Xf.p;
-  *Y = h->Yf.p;
+  *X = s.Xf.p;
+  *Y = s.Yf.p;
   return 0;
 }
 
-// Solve with the factors in h->f: y = round_out(M^{-1} t) with components in comp.
+// Inverses of caller-supplied factors (format f, n x n, ld n) in precision p, held in
+// the external slot; the current slot is left unchanged.
+static int external_inverses(msir_handle* h, int n, int f, const void* dW, int p, const void** X, const void** Y) {
+  FactorSlot* saved = h->cur;
+  FactorSlot& e = h->slot[kExtSlot];
+  h->cur = &e;
+  e.f.prec = f; e.f.n = n; e.f.W = (void*)dW; e.f.Wbytes = 0;
+  e.inv64 = e.inv32 = false;
+  int rc = ensure_inverses(h, n, p, X, Y);
+  e.f.W = nullptr;          // not owned
+  e.inv64 = e.inv32 = false;
+  h->cur = saved;
+  return rc;
+}
+
+// Solve with the current factors: y = round_out(M^{-1} t) with components in comp.
 static int solve_with(msir_handle* h, int n, int comp, const double* t_hi, const double* t_lo, double* y,
                       int out_round, int mode) {
-  FactorState& f = h->f;
+  FactorState& f = h->cur->f;
   TrsvArgs a;
   a.n = n; a.prec = f.prec; a.W = f.W; a.ldw = n; a.perm = f.perm; a.rinv = f.rinv;
   a.R = f.scaled ? f.R : nullptr; a.S = f.scaled ? f.S : nullptr; a.mu = f.scaled ? f.mu : 1.0;
@@ -492,10 +536,14 @@ int msir_destroy(msir_handle* h) {
   Ctx& c = h->c;
   DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.part_x, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
                     &c.tmp_scalar, &c.moved, &c.tr_part, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
-                    &h->tmp2, &h->Xd, &h->Yd, &h->Xf, &h->Yf, &h->Acsr};
+                    &h->tmp2, &h->Acsr};
   for (DevBuf* b : bufs) c.release(b->p, b->bytes);
-  if (h->f.W) c.release(h->f.W, h->f.Wbytes);
-  if (h->f.rinv) c.release(h->f.rinv, h->f.vec_bytes);
+  for (FactorSlot& s : h->slot) {
+    DevBuf* ib[] = {&s.Xd, &s.Yd, &s.Xf, &s.Yf};
+    for (DevBuf* b : ib) c.release(b->p, b->bytes);
+    if (s.f.W && s.f.Wbytes) c.release(s.f.W, s.f.Wbytes);
+    if (s.f.rinv) c.release(s.f.rinv, s.f.vec_bytes);
+  }
   h->gw.free_all(c);
   c.release(c.blockmax, 0);
   if (c.ev_pool) {
@@ -621,12 +669,7 @@ int msir_getrs(msir_handle* h, int n, msir_prec f, const void* dW, int ldw, cons
   if (mode == 1) {
     // apply through the explicit inverses of L and U in precision comp
     const void *X, *Y;
-    FactorState saved = h->f;
-    h->f.prec = f; h->f.W = (void*)dW;
-    h->inv64 = h->inv32 = false;
-    rc = ensure_inverses(h, n, comp, &X, &Y);
-    h->f = saved;
-    h->inv64 = h->inv32 = false;
+    rc = external_inverses(h, n, f, dW, comp, &X, &Y);
     if (rc) return rc;
     double* t2 = vbuf(h, h->tmp2, n);
     if (!t2) return MSIR_ERR_ALLOC;
@@ -772,12 +815,7 @@ int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, co
   if (p != MSIR_DD) {
     // inverses of the caller's factors (the handle's cached inverses are invalidated)
     if (ldw != n) return -7;
-    FactorState saved = h->f;
-    h->f.prec = f; h->f.W = (void*)dW;
-    h->inv64 = h->inv32 = false;
-    rc = ensure_inverses(h, n, p, &op.Xinv, &op.Yinv);
-    h->f = saved;
-    h->inv64 = h->inv32 = false;
+    rc = external_inverses(h, n, f, dW, p, &op.Xinv, &op.Yinv);
     if (rc) return rc;
     op.inv_prec = p;
   }
@@ -797,6 +835,24 @@ int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_prec f, co
 static int solve_one(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx,
                      const double* dxt, const msir_params& P, msir_result* out, std::vector<msir_step>& hist);
 
+// Validity of a parameter set for order n (0 or the msir_solve argument code -8; -7
+// when CONV_TRUE lacks x_true).
+static int check_params(int n, const msir_params& P, bool have_xt) {
+  if (P.uf < MSIR_FP16 || P.uf > MSIR_FP64) return -8;
+  if (P.u != MSIR_FP32 && P.u != MSIR_FP64) return -8;
+  if (P.ur != MSIR_FP64 && P.ur != MSIR_DD) return -8;
+  if (P.ux != MSIR_FP64 && P.ux != P.u) return -8;
+  if (P.i_max < 1 || !(P.rho_thresh > 0) || P.restart < 0 || P.max_steps < 1) return -8;
+  if (P.conv < MSIR_CONV_ESTIMATE || P.conv > MSIR_CONV_COMPONENTWISE) return -8;
+  if (P.conv == MSIR_CONV_TRUE && !have_xt) return -7;
+  if (P.nb != 0) {   // an explicit panel width must suit every factor format the ladder can reach
+    for (int f = P.uf; f >= 0; f = next_uf(f))
+      if (!nb_ok(n, f, P.nb)) return -8;
+  }
+  if (P.lu_update != MSIR_LU_MFMA && P.lu_update != MSIR_LU_FMA) return -8;
+  return 0;
+}
+
 int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* db, double* dx, const double* dxt,
                const msir_params* params, msir_result* out, msir_step* hist, int hist_cap, int* hist_len) {
   if (!h) return -1;
@@ -807,17 +863,10 @@ int msir_solve(msir_handle* h, int n, const double* dA, int lda, const double* d
   if (!dx) return -6;
   msir_params P;
   if (params) P = *params; else msir_params_default(&P);
-  if (P.uf < MSIR_FP16 || P.uf > MSIR_FP64) return -8;
-  if (P.u != MSIR_FP32 && P.u != MSIR_FP64) return -8;
-  if (P.ur != MSIR_FP64 && P.ur != MSIR_DD) return -8;
-  if (P.ux != MSIR_FP64 && P.ux != P.u) return -8;
-  if (P.i_max < 1 || !(P.rho_thresh > 0) || P.restart < 0 || P.max_steps < 1) return -8;
-  if (P.conv < MSIR_CONV_ESTIMATE || P.conv > MSIR_CONV_COMPONENTWISE) return -8;
-  if (P.conv == MSIR_CONV_TRUE && !dxt) return -7;
-  if (P.nb != 0 && !nb_ok(n, P.uf, P.nb)) return -8;
-  if (P.lu_update != MSIR_LU_MFMA && P.lu_update != MSIR_LU_FMA) return -8;
+  if (int e = check_params(n, P, dxt != nullptr)) return e;
   if (hist_cap < 0) return -11;
   HIP_CHECK(hipSetDevice(h->c.device));
+  if (!h->share) invalidate_factors(h);
   std::vector<msir_step> H;
   int rc = solve_one(h, n, dA, lda, db, dx, dxt, P, out, H);
   unsigned terr = 0;
@@ -836,9 +885,10 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
   int rc;
   const double k_max = P.k_max > 0 ? P.k_max : 0.1 * n;
   int uf = P.uf, u = P.u, ur = P.ur;
-  const int ux = P.ux;
+  int ux = P.ux;
+  const bool ux_follows_u = P.ux == P.u;   // Alg. 4 stores x in u, also after u is lowered
   const int u0 = u;
-  const double uxr = unit_roundoff(ux);
+  double uxr = unit_roundoff(ux);
   const double sqn = sqrt((double)n);
   auto tau_of = [&](int uu) { return P.tau > 0 ? P.tau : (uu == P_FP32 ? 1e-6 : 1e-10); };
   const int nb = P.nb;
@@ -863,20 +913,23 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
   if (rc) return rc;
   const double normA = h->host_small[0], normb = h->host_small[1];
 
+  const int fact0 = h->factorizations;
   rc = do_factor(h, n, dA, lda, uf, P.scaling, nb, P.lu_update);
   if (rc) return rc;
-  int n_lu = 1;
   float* Au = nullptr;
   if (u == P_FP32) {
     Au = (float*)c.grow(h->Au, (size_t)n * n * sizeof(float));
     if (!Au) return MSIR_ERR_ALLOC;
-    rc = to_fp32(c, n, dA, lda, Au, n);
-    if (rc) return rc;
+    if (!(h->share && h->au_valid)) {
+      rc = to_fp32(c, n, dA, lda, Au, n);
+      if (rc) return rc;
+      h->au_valid = h->share;
+    }
   }
   HIP_CHECK(hipEventRecord(h->ev[1], c.stream));
   float t_factor = 0.0f;
 
-  unsigned ev_pending = h->f.scaled ? MSIR_EV_SCALED : 0u;
+  unsigned ev_pending = h->cur->f.scaled ? MSIR_EV_SCALED : 0u;
   // x0 by substitution in u_f
   rc = solve_with(h, n, uf, db, nullptr, x0, -1, 0);
   if (rc) return rc;
@@ -986,11 +1039,11 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
       rc = solve_with(h, n, uf, rhat, nullptr, d, u, 0);
       if (rc) return rc;
     } else {
-      op.u = u; op.p = (alg == 1) ? u : square_of(u); op.prec = h->f.prec; op.Au = Au;
-      op.W = h->f.W; op.ldw = n; op.perm = h->f.perm; op.rinv = h->f.rinv;
-      op.R = h->f.scaled ? h->f.R : nullptr; op.S = h->f.scaled ? h->f.S : nullptr;
-      op.mu = h->f.scaled ? h->f.mu : 1.0;
-      op.pinv = h->f.pinv; op.Rp = h->f.scaled ? h->f.Rp : nullptr;
+      op.u = u; op.p = (alg == 1) ? u : square_of(u); op.prec = h->cur->f.prec; op.Au = Au;
+      op.W = h->cur->f.W; op.ldw = n; op.perm = h->cur->f.perm; op.rinv = h->cur->f.rinv;
+      op.R = h->cur->f.scaled ? h->cur->f.R : nullptr; op.S = h->cur->f.scaled ? h->cur->f.S : nullptr;
+      op.mu = h->cur->f.scaled ? h->cur->f.mu : 1.0;
+      op.pinv = h->cur->f.pinv; op.Rp = h->cur->f.scaled ? h->cur->f.Rp : nullptr;
       op.Xinv = op.Yinv = nullptr;
       op.inv_prec = -1;
       if (op.p != P_DD) {
@@ -1081,6 +1134,7 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
         if (nuf < 0) { status = MSIR_NOT_CONVERGED; goto done; }
         uf = nuf;
         if (unit_roundoff(uf) < unit_roundoff(u)) u = uf;
+        if (ux_follows_u) { ux = u; uxr = unit_roundoff(ux); }
         if (unit_roundoff(ur) > unit_roundoff(u) * unit_roundoff(u)) ur = square_of(u);
         level += 1;
         {
@@ -1089,8 +1143,7 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
           rc = do_factor(h, n, dA, lda, uf, P.scaling, nb, P.lu_update);
           if (rc) return rc;
         }
-        n_lu += 1;
-        ev_pending = h->f.scaled ? MSIR_EV_SCALED : 0u;
+        ev_pending = h->cur->f.scaled ? MSIR_EV_SCALED : 0u;
         alg = 0;
         cached = false;   // u or u_r may have changed: the scaled residual must be recomputed
         continue;
@@ -1124,7 +1177,7 @@ done:
     out->cged = cged ? 1 : 0;
     out->status = status;
     out->steps = (int)hist.size();
-    out->n_lu = n_lu;
+    out->n_lu = h->factorizations - fact0;
     out->gmres_iters = gm_total;
     out->final_uf = uf; out->final_u = u; out->final_ur = ur;
     HIP_CHECK(hipEventSynchronize(h->ev[2]));
@@ -1136,7 +1189,7 @@ done:
   }
   (void)t_factor;
   HIP_CHECK(hipStreamSynchronize(c.stream));
-  if (!cged && h->f.prec == P_FP64 && h->f.info > 0) status = MSIR_SINGULAR;
+  if (!cged && h->cur->f.prec == P_FP64 && h->cur->f.info > 0) status = MSIR_SINGULAR;
   return status;
 }
 
@@ -1186,11 +1239,11 @@ static int ir5_one(msir_handle* h, int n, const double* dA, int lda, const doubl
   }
   GmresOp op;
   op.n = n; op.A = dA; op.lda = lda; op.tmp_hi = th; op.tmp_lo = tl; op.tmp2 = t2; op.mode = 0; op.dinv = nullptr;
-  op.u = ug; op.p = up; op.prec = h->f.prec; op.Au = Au;
-  op.W = h->f.W; op.ldw = n; op.perm = h->f.perm; op.rinv = h->f.rinv;
-  op.R = h->f.scaled ? h->f.R : nullptr; op.S = h->f.scaled ? h->f.S : nullptr;
-  op.mu = h->f.scaled ? h->f.mu : 1.0;
-  op.pinv = h->f.pinv; op.Rp = h->f.scaled ? h->f.Rp : nullptr;
+  op.u = ug; op.p = up; op.prec = h->cur->f.prec; op.Au = Au;
+  op.W = h->cur->f.W; op.ldw = n; op.perm = h->cur->f.perm; op.rinv = h->cur->f.rinv;
+  op.R = h->cur->f.scaled ? h->cur->f.R : nullptr; op.S = h->cur->f.scaled ? h->cur->f.S : nullptr;
+  op.mu = h->cur->f.scaled ? h->cur->f.mu : 1.0;
+  op.pinv = h->cur->f.pinv; op.Rp = h->cur->f.scaled ? h->cur->f.Rp : nullptr;
   op.Xinv = op.Yinv = nullptr;
   op.inv_prec = -1;
   if (up != P_DD) {
@@ -1200,7 +1253,7 @@ static int ir5_one(msir_handle* h, int n, const double* dA, int lda, const doubl
   }
   HIP_CHECK(hipEventRecord(h->ev[1], c.stream));
 
-  unsigned ev = h->f.scaled ? MSIR_EV_SCALED : 0u;
+  unsigned ev = h->cur->f.scaled ? MSIR_EV_SCALED : 0u;
   double* x = xa;
   double* xn = xb;
   rc = solve_with(h, n, uf, db, nullptr, x, -1, 0);
@@ -1464,7 +1517,8 @@ int msir_timing_get(msir_handle* h, int cls, long long* launches, double* total_
 }
 
 int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda, const double* dB, int ldb,
-                     double* dX, int ldx, const msir_params* params, msir_result* outs) {
+                     double* dX, int ldx, const double* dXt, int ldxt, const msir_params* params,
+                     msir_result* outs, msir_step* hist, int hist_cap, int* hist_len) {
   if (!h) return -1;
   if (n < 1 || n > MSIR_MAX_N) return MSIR_ERR_SIZE;
   if (nrhs < 1) return -3;
@@ -1474,14 +1528,38 @@ int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda,
   if (ldb < n) return -7;
   if (!dX) return -8;
   if (ldx < n) return -9;
+  if (dXt && ldxt < n) return -11;
+  msir_params P;
+  if (params) P = *params; else msir_params_default(&P);
+  if (int e = check_params(n, P, dXt != nullptr)) return e == -7 ? -10 : -12;
+  if (hist_cap < 0) return -15;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  // one independent controller per column over a factor cache with one slot per
+  // factor format: a level is factored by the first column that reaches it
+  invalidate_factors(h);
+  h->share = true;
   int worst = 0;
+  int rc = 0;
+  std::vector<msir_step> H;
   for (int j = 0; j < nrhs; ++j) {
-    int rc = msir_solve(h, n, dA, lda, dB + (size_t)j * ldb, dX + (size_t)j * ldx, nullptr, params,
-                        outs ? outs + j : nullptr, nullptr, 0, nullptr);
-    if (rc < 0) return rc;
+    H.clear();
+    rc = solve_one(h, n, dA, lda, dB + (size_t)j * ldb, dX + (size_t)j * ldx,
+                   dXt ? dXt + (size_t)j * ldxt : nullptr, P, outs ? outs + j : nullptr, H);
+    if (rc < 0) break;
+    unsigned terr = 0;
+    if (trsv_check(h->c, &terr) == 0 && terr) {
+      msir_set_error("substitution wait expired", __FILE__, __LINE__);
+      rc = MSIR_ERR_TIMEOUT;
+      break;
+    }
+    if (hist_len) hist_len[j] = (int)H.size();
+    if (hist && hist_cap > 0)
+      memcpy(hist + (size_t)j * hist_cap, H.data(), std::min((size_t)hist_cap, H.size()) * sizeof(msir_step));
     worst = std::max(worst, rc);
   }
-  return worst;
+  h->share = false;
+  invalidate_factors(h);
+  return rc < 0 ? rc : worst;
 }
 
 int msir_solve_batched(msir_handle* h, int count, const int* n, const double* const* dA, const int* lda,

@@ -73,7 +73,8 @@ _SIG = {
                             ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_gmres_ir5": (_I, [_P, _I, _P, _I, _P, _P, _P, ctypes.POINTER(Params), _I, _I, ctypes.POINTER(Result),
                             ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
-    "msir_solve_multi": (_I, [_P, _I, _I, _P, _I, _P, _I, _P, _I, ctypes.POINTER(Params), ctypes.POINTER(Result)]),
+    "msir_solve_multi": (_I, [_P, _I, _I, _P, _I, _P, _I, _P, _I, _P, _I, ctypes.POINTER(Params),
+                              ctypes.POINTER(Result), ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_solve_batched": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_P), ctypes.POINTER(_I),
                                 ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(Params),
                                 ctypes.POINTER(Result)]),
@@ -246,16 +247,24 @@ def gmres_ir5(h, A, b, ug, up, x_true=None, P=None, hist_cap=4096, x=None):
     return x, res, [H[i] for i in range(min(hl.value, hist_cap))], rc
 
 
-def solve_multi(h, A, B, P=None):
+def solve_multi(h, A, B, X_true=None, P=None, hist_cap=512, X=None):
+    """Alg. 4 for the columns of B over one factor cache.  Returns
+    (X, [Result per column], [[Step...] per column], worst status)."""
     A = colmajor(A)
     B = colmajor(B)
     n, nrhs = B.shape
-    X = colmajor(torch.empty(n, nrhs, dtype=torch.float64, device=A.device))
+    if X is None:
+        X = colmajor(torch.empty(n, nrhs, dtype=torch.float64, device=A.device))
+    Xt = colmajor(X_true) if X_true is not None else None
     outs = (Result * nrhs)()
-    rc = lib().msir_solve_multi(h.h, n, nrhs, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(X), _ld(X),
-                                ctypes.byref(P) if P is not None else None, outs)
+    H = (Step * (hist_cap * nrhs))()
+    hl = (ctypes.c_int * nrhs)()
+    rc = lib().msir_solve_multi(h.h, n, nrhs, _ptr(A), _ld(A), _ptr(B), _ld(B), _ptr(X), _ld(X), _ptr(Xt),
+                                _ld(Xt) if Xt is not None else n, ctypes.byref(P) if P is not None else None,
+                                outs, H, hist_cap, hl)
     _check(rc, "msir_solve_multi")
-    return X, [outs[i] for i in range(nrhs)], rc
+    hists = [[H[j * hist_cap + i] for i in range(min(hl[j], hist_cap))] for j in range(nrhs)]
+    return X, [outs[i] for i in range(nrhs)], hists, rc
 
 
 def solve_batched(h, As, bs, P=None):

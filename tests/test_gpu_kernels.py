@@ -172,11 +172,23 @@ def test_getrf_manufactured_pivots_bitexact(M, h, fmt, n, nb):
     np.testing.assert_array_equal(ipiv.cpu().numpy(), po)
 
 
+def pivot_margin(n, seed, fmt):
+    """Random matrix with a pivot margin: in column k the entry of row order[k] is
+    4-16 times larger than any other entry (before and, by a margin that the
+    rounding of the trailing updates cannot close, after elimination), so GEPP
+    picks order[k] at step k on both sides whatever the accumulation order."""
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(n)
+    A = rng.uniform(-1, 1, (n, n))
+    for k, r in enumerate(order):
+        A[r, k] = (4.0 * n) * rng.uniform(1.0, 4.0) * (1 if k % 2 else -1)
+    return F.round_to(A, fmt)
+
+
 @pytest.mark.parametrize("fmt,n,nb", [("fp16", 200, 64), ("fp16", 333, 16), ("bf16", 200, 32),
                                       ("fp32", 200, 16), ("fp64", 150, 16), ("fp32", 300, 64), ("fp64", 300, 32)])
 def test_getrf_blocked_vs_oracle(M, h, fmt, n, nb):
-    rng = np.random.default_rng(n + nb)
-    Af = F.round_to(rng.standard_normal((n, n)), fmt)
+    Af = pivot_margin(n, n + nb, fmt)
     W = to_dev_fmt(Af, fmt, M)
     ipiv, info = M.getrf(h, W, fmt, nb)   # matrix-core trailing update
     Wo, po, io = OLU.getrf(Af, fmt, nb, trailing="exact")
@@ -187,17 +199,18 @@ def test_getrf_blocked_vs_oracle(M, h, fmt, n, nb):
     p = OLU.perm_from_piv(piv)
     E = np.abs(Af[p] - L @ U)
     g = (n / nb + n * F.u("fp32") / F.u(fmt) + 3) * F.u(fmt)
-    assert np.all(E <= g / (1 - g) * (np.abs(L) @ np.abs(U)) + 1e-300)
+    # fp16 multipliers below 2^-14 are subnormal: their rounding error is absolute
+    # (at most 2^-25), which adds up to 2^-25 |u_jj| per product to the bound
+    tiny = 2.0 ** -24 * np.abs(U).max() if fmt == "fp16" else 1e-300
+    assert np.all(E <= g / (1 - g) * (np.abs(L) @ np.abs(U)) + tiny)
     # Agreement with the oracle.  The two sides differ only in the order of the
-    # float32 (float64) accumulation of the trailing update; the resulting
-    # rounding differences propagate through later Schur complements, amplified
-    # by at most the condition number, and may flip a near-tie pivot choice
-    # (random matrices have no pivot margin; see the manufactured-pivot and
-    # exact-arithmetic tests for bit-exact agreement).
-    if np.array_equal(piv, po):
-        kap = np.linalg.cond(Af, np.inf)
-        rel = np.abs(Wg - Wo).max() / np.abs(Wo).max()
-        assert rel <= 4 * kap * F.u(fmt), (rel, kap)
+    # float32 (float64) accumulation of the trailing update; with the pivot margin
+    # the pivots must be equal, and the rounding differences propagate through
+    # later Schur complements, amplified by at most the condition number.
+    np.testing.assert_array_equal(piv, po)
+    kap = np.linalg.cond(Af, np.inf)
+    rel = np.abs(Wg - Wo).max() / np.abs(Wo).max()
+    assert rel <= 4 * kap * F.u(fmt), (rel, kap)
 
 
 @pytest.mark.parametrize("fmt,n,nb", [("fp16", 100, 16), ("fp16", 96, 32), ("fp16", 130, 64),
@@ -225,6 +238,42 @@ def test_getrf_exact_arithmetic_bitexact(M, h, fmt, n, nb):
         np.testing.assert_array_equal(ipiv.cpu().numpy(), po)
         np.testing.assert_array_equal(host_w(W, fmt), Wo)
         np.testing.assert_array_equal(Wo, np.tril(L0, -1) + U0)
+
+
+@pytest.mark.parametrize("fmt,n,nb", [("fp16", 4096, 16), ("bf16", 4096, 16), ("fp32", 4096, 16),
+                                      ("fp16", 8192, 8), ("bf16", 8192, 8), ("fp64", 4096, 8)])
+def test_getrf_exact_arithmetic_full_size(M, h, fmt, n, nb):
+    """The exact-arithmetic construction at the workloads' full sizes (panels of four
+    and eight rows per thread, the launch configuration of the benchmark): a sparse
+    unit lower L0 (about four entries in {1/4, 1/2} per row) and an integer U0 keep
+    every entry of A and of every Schur complement a small quarter-integer, exact in
+    the factor format and in the fp32 accumulator, so both trailing updates must
+    return exactly (P0, L0, U0).  Built and compared on the device (n^2 entries)."""
+    g = torch.Generator(device=DEV).manual_seed(n + nb)
+    dt = torch.float64
+    mask = torch.rand((n, n), generator=g, device=DEV, dtype=dt) < (4.0 / n)
+    vals = torch.tensor([0.25, -0.25, 0.5, -0.5], device=DEV, dtype=dt)
+    L0 = torch.tril(torch.where(mask, vals[torch.randint(0, 4, (n, n), generator=g, device=DEV)], 0.0), -1)
+    L0 += torch.eye(n, device=DEV, dtype=dt)
+    U0 = torch.triu(torch.randint(-4, 5, (n, n), generator=g, device=DEV).to(dt), 1)
+    dvals = torch.tensor([4.0, -4.0, 8.0, -8.0], device=DEV, dtype=dt)
+    U0 += torch.diag(dvals[torch.randint(0, 4, (n,), generator=g, device=DEV)])
+    P0 = torch.randperm(n, generator=g, device=DEV)
+    A = torch.empty((n, n), device=DEV, dtype=dt)
+    A[P0] = L0 @ U0
+    want = (torch.tril(L0, -1) + U0)
+    tdt = M.TORCH_DTYPE[M.PREC[fmt]]
+    assert torch.equal(A.to(tdt).to(dt), A)
+    for update in ("mfma", "fma"):
+        W = M.colmajor(A.to(tdt))
+        ipiv, info = M.getrf(h, W, fmt, nb, update=update)
+        assert info == 0
+        assert torch.equal(W.to(dt), want), update
+        # interchanges -> permutation: (P A)[i] = A[perm[i]] must put row P0[i] at i
+        piv = ipiv.cpu().numpy()
+        perm = OLU.perm_from_piv(piv)
+        np.testing.assert_array_equal(perm, P0.cpu().numpy())
+        del W
 
 
 @pytest.mark.parametrize("fmt,n,nb", [("fp16", 200, 64), ("fp16", 333, 16), ("bf16", 200, 32), ("fp16", 1100, 32),
