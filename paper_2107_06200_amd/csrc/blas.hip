@@ -226,31 +226,50 @@ static int nsplit_for(int n) {
   return s;
 }
 
-int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
-             double* rhat, double* s_dev, bool want_true) {
+size_t residual_scratch_doubles(int n, int ur, bool want_true) {
+  const GemvPlan g = gemv_plan(n, 0);
+  const size_t part = (size_t)g.ns * n;
+  const int rb = (n + RT - 1) / RT;
+  const size_t parts = part * (ur == P_DD ? 2 : want_true ? 3 : 1);
+  return parts + (ur == P_DD ? 2 : 1) * (size_t)n + 2 * (size_t)rb;
+}
+
+int residual_with(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
+                  double* rhat, double* s_dev, bool want_true, const ResidWork& w) {
   const GemvPlan g = gemv_plan(n, 0);
   const int ns = c.sp ? 1 : g.ns;   // a sparse A gives one slice
   const int rb = (n + RT - 1) / RT;
-  double* ph = c.ws_part_hi(ns * (size_t)n);
-  double* pl = c.ws_part_lo(ns * (size_t)n);
-  double* px = c.ws_part_x(ns * (size_t)n);
-  double* rh = c.ws_r_hi(n);
-  double* rl = c.ws_r_lo(n);
-  if (!ph || !pl || !px || !rh || !rl) return MSIR_ERR_ALLOC;
   const int mode = (ur == P_DD) ? 1 : (want_true ? 2 : 0);
+  double *ph = w.ph, *pl = w.pl, *px = w.px, *rh = w.rh, *rl = w.rl;
   const int _slot = c.tbegin(MSIR_T_RESID);
   int rc = c.sp ? spmv_partials(c, n, *c.sp, false, x, nullptr, mode, ph, pl, px, nullptr)
                 : gemv_partials(c, g, n, P_FP64, A, lda, x, nullptr, nullptr, mode, ph, pl, px, nullptr);
   if (rc) return rc;
   if (mode == 1)
-    k_resid_finish<1><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
+    k_resid_finish<1><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, w.blockmax, w.counter, u, rhat, s_dev);
   else if (mode == 2)
-    k_resid_finish<2><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, px, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
+    k_resid_finish<2><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, px, b, rh, rl, w.blockmax, w.counter, u, rhat, s_dev);
   else
-    k_resid_finish<0><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, c.blockmax, c.counter, u, rhat, s_dev);
+    k_resid_finish<0><<<rb, RT, 0, c.stream>>>(n, ns, ph, pl, nullptr, b, rh, rl, w.blockmax, w.counter, u, rhat, s_dev);
   c.tend(_slot);
   HIP_CHECK(hipGetLastError());
   return 0;
+}
+
+int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
+             double* rhat, double* s_dev, bool want_true) {
+  const GemvPlan g = gemv_plan(n, 0);
+  const int ns = c.sp ? 1 : g.ns;
+  ResidWork w;
+  w.ph = c.ws_part_hi(ns * (size_t)n);
+  w.pl = c.ws_part_lo(ns * (size_t)n);
+  w.px = c.ws_part_x(ns * (size_t)n);
+  w.rh = c.ws_r_hi(n);
+  w.rl = c.ws_r_lo(n);
+  if (!w.ph || !w.pl || !w.px || !w.rh || !w.rl) return MSIR_ERR_ALLOC;
+  w.blockmax = c.blockmax;
+  w.counter = c.counter;
+  return residual_with(c, n, A, lda, x, b, ur, u, rhat, s_dev, want_true, w);
 }
 
 // ------------------------------------------------------------------ A v in precision p

@@ -89,6 +89,17 @@ int scaling(Ctx& c, int n, const double* A, int lda, int prec, int rows, double*
 // residual when want_true (or ur == DD); rhat = fl_u(r / s_dev[0]) if rhat != null.
 int residual(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
              double* rhat, double* s_dev, bool want_true);
+// Device buffers of one residual: slice partial sums (ph; pl for double-double, px for
+// the float64 sums beside them), r (rh, rl for double-double), per-block maxima (2 per
+// 256 rows) and the last-block counter (zero between launches; the last block resets it).
+struct ResidWork {
+  double *ph = nullptr, *pl = nullptr, *px = nullptr, *rh = nullptr, *rl = nullptr, *blockmax = nullptr;
+  unsigned* counter = nullptr;
+};
+int residual_with(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
+                  double* rhat, double* s_dev, bool want_true, const ResidWork& w);
+// Doubles of those buffers (besides the counter) for a dense A of order n.
+size_t residual_scratch_doubles(int n, int ur, bool want_true);
 // y = fl_p(A v); with operm (p != DD) y[i] = oR[q] * fl_p(A v)_q, q = operm[i].
 int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
            double* y_hi, double* y_lo, const int* skip, const int* operm = nullptr, const double* oR = nullptr);
