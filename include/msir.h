@@ -289,6 +289,24 @@ MSIR_API int msir_gmres(msir_handle* h, int n, const double* dA, int lda, msir_p
                const double* drhat, msir_prec u, msir_prec p, double tau, double k_max,
                int restart, double* dd, int* k);
 
+/* msir_residual for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with every scratch buffer (slice partial sums, r, block
+ * maxima, the last-block counter) in one fixed device array of
+ * MSIR_NOALLOC_SCRATCH_BYTES per GPU, held by the library until the process ends,
+ * instead of the handle's workspace.  The call allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine); the handle (created beforehand) supplies
+ * the stream and its preallocated pinned memory for s.  Arguments, layout and return
+ * values as for msir_residual; n up to MSIR_NOALLOC_MAX_N (else MSIR_ERR_SIZE);
+ * MSIR_ERR_HIP if the array's address could not be obtained when the device's first
+ * handle was created.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (other streams, other threads, other handles) race and must be
+ * serialized by the caller.                                                       */
+#define MSIR_NOALLOC_MAX_N          8192
+#define MSIR_NOALLOC_SCRATCH_BYTES  (2u << 20)
+MSIR_API int msir_residual_noalloc(msir_handle* h, int n, const double* dA, int lda, const double* dx,
+                                   const double* db, msir_prec ur, msir_prec u, double* drhat, double* s);
+
 /* Normwise and componentwise backward errors of x (Sec. 2, error measures), the
  * residual formed in double-double: nbe = ||b-Ax||_inf/(||A||_inf ||x||_inf +
  * ||b||_inf), cbe = max_i |b-Ax|_i / (|A||x| + |b|)_i.                           */

@@ -525,6 +525,9 @@ int msir_create(msir_handle** hp, int device, size_t budget, void* stream) {
   if (h->c.alloc((void**)&h->c.blockmax, Ctx::kMaxBlocks * sizeof(double) * 2)) { delete h; return MSIR_ERR_ALLOC; }
   HIP_CHECK(hipHostMalloc((void**)&h->host_small, 64 * sizeof(double)));
   for (int i = 0; i < 4; ++i) HIP_CHECK(hipEventCreate(&h->ev[i]));
+  // address of the allocation-free entry point's scratch array on this device (once
+  // per device; a failure is reported by that entry point only)
+  (void)noalloc_init(device);
   *hp = h;
   return 0;
 }
@@ -720,6 +723,27 @@ int msir_residual(msir_handle* h, int n, const double* dA, int lda, const double
   HIP_CHECK(hipSetDevice(h->c.device));
   double* sdev = h->dev_small + 24;
   int rc = residual(h->c, n, dA, lda, dx, db, ur, u, drhat, sdev, false);
+  if (rc) return rc;
+  rc = sync_read(h, sdev, 1);
+  if (rc) return rc;
+  if (s) *s = h->host_small[0];
+  return 0;
+}
+
+int msir_residual_noalloc(msir_handle* h, int n, const double* dA, int lda, const double* dx, const double* db,
+                          msir_prec ur, msir_prec u, double* drhat, double* s) {
+  if (!h) return -1;
+  if (n < 1 || n > MSIR_NOALLOC_MAX_N) return MSIR_ERR_SIZE;
+  if (!dA) return -3;
+  if (lda < n) return -4;
+  if (!dx) return -5;
+  if (!db) return -6;
+  if (ur != MSIR_FP64 && ur != MSIR_DD) return -7;
+  if (u < MSIR_FP16 || u > MSIR_FP64) return -8;
+  if (!drhat) return -9;
+  HIP_CHECK(hipSetDevice(h->c.device));
+  double* sdev = h->dev_small + 24;
+  int rc = residual_noalloc(h->c, n, dA, lda, dx, db, ur, u, drhat, sdev);
   if (rc) return rc;
   rc = sync_read(h, sdev, 1);
   if (rc) return rc;

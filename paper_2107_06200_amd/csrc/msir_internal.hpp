@@ -100,6 +100,11 @@ int residual_with(Ctx& c, int n, const double* A, int lda, const double* x, cons
                   double* rhat, double* s_dev, bool want_true, const ResidWork& w);
 // Doubles of those buffers (besides the counter) for a dense A of order n.
 size_t residual_scratch_doubles(int n, int ur, bool want_true);
+// The allocation-free residual (noalloc.hip): noalloc_init once per device (device
+// current), then residual_noalloc with the per-device scratch array.
+int noalloc_init(int device);
+int residual_noalloc(Ctx& c, int n, const double* A, int lda, const double* x, const double* b, int ur, int u,
+                     double* rhat, double* s_dev);
 // y = fl_p(A v); with operm (p != DD) y[i] = oR[q] * fl_p(A v)_q, q = operm[i].
 int matvec(Ctx& c, int n, const double* A, int lda, const float* Au, int ldau, const double* v, int p,
            double* y_hi, double* y_lo, const int* skip, const int* operm = nullptr, const double* oR = nullptr);

@@ -54,7 +54,7 @@ class Result(ctypes.Structure):
 
 SYMBOLS = ["msir_create", "msir_destroy", "msir_params_default", "msir_nb_auto", "msir_workspace_bytes",
            "msir_status_string", "msir_solve", "msir_solve_csr", "msir_gmres_ir5", "msir_solve_multi", "msir_solve_batched", "msir_convert",
-           "msir_scaling", "msir_getrf", "msir_getrs", "msir_round", "msir_residual", "msir_gmres", "msir_backward_error",
+           "msir_scaling", "msir_getrf", "msir_getrs", "msir_round", "msir_residual", "msir_residual_noalloc", "msir_gmres", "msir_backward_error",
            "msir_timing", "msir_timing_get"]
 
 _P = ctypes.c_void_p
@@ -84,6 +84,7 @@ _SIG = {
     "msir_getrs": (_I, [_P, _I, _I, _P, _I, _P, _P, _P, _D, _I, _I, _P, _P]),
     "msir_round": (_I, [_P, _I, _I, _P, _P]),
     "msir_residual": (_I, [_P, _I, _P, _I, _P, _P, _I, _I, _P, ctypes.POINTER(_D)]),
+    "msir_residual_noalloc": (_I, [_P, _I, _P, _I, _P, _P, _I, _I, _P, ctypes.POINTER(_D)]),
     "msir_gmres": (_I, [_P, _I, _P, _I, _I, _P, _I, _P, _P, _P, _D, _P, _I, _I, _D, _D, _I, _P,
                         ctypes.POINTER(_I)]),
     "msir_backward_error": (_I, [_P, _I, _P, _I, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(_D)]),
@@ -352,6 +353,18 @@ def residual(h, A, x, b, ur, u):
     s = ctypes.c_double(0)
     _check(lib().msir_residual(h.h, n, _ptr(A), _ld(A), _ptr(x), _ptr(b), _prec(ur), _prec(u), _ptr(rhat),
                                ctypes.byref(s)), "msir_residual")
+    return rhat, s.value
+
+
+def residual_noalloc(h, A, x, b, ur, u, rhat=None):
+    """msir_residual_noalloc: as residual(), with the library's fixed scratch array."""
+    A = colmajor(A)
+    n = A.shape[0]
+    if rhat is None:
+        rhat = torch.empty(n, dtype=torch.float64, device=A.device)
+    s = ctypes.c_double(0)
+    _check(lib().msir_residual_noalloc(h.h, n, _ptr(A), _ld(A), _ptr(x), _ptr(b), _prec(ur), _prec(u), _ptr(rhat),
+                                       ctypes.byref(s)), "msir_residual_noalloc")
     return rhat, s.value
 
 
