@@ -22,15 +22,23 @@ whenever they are written back to the matrix:
        the arithmetic format (row c uses rows 0..c-1 in increasing order),
        then rounded to u_f.
     3. A22 <- fl_f(fl_arith(A22 - L21 U12)), the product being formed from the
-       stored u_f values (products of two u_f numbers are exact in float64).
+       stored u_f values: in fp32 arithmetic a chain of single-rounded fp32 fused
+       multiply-adds in increasing k (the default; trailing="exact" rounds the
+       exact float64 product once instead, a comparison model only); in float64
+       arithmetic the products summed in increasing k, then subtracted.
 
 For u_f = fp64 the panel and triangular updates use separately rounded
-float64 multiply and subtract.  ``piv`` uses LAPACK's convention (0-based):
+float64 multiply and subtract.  From order NATIVE_MIN_N on (the trailing chain
+or float64 arithmetic) the same steps run as plain C loops (oracle/native/dm_lu.c,
+pinned bit for bit against these Python loops) when that library is built.  ``piv`` uses LAPACK's convention (0-based):
 at step j rows j and piv[j] were interchanged.
 """
 import numpy as np
 
+from . import native as _native
 from .fmt import fma32, round_to
+
+NATIVE_MIN_N = 384
 
 
 def nb_auto(n, fmt_f):
@@ -52,16 +60,25 @@ def _fma(wa):
     return lambda a, b, c: c + a * b          # float64, two roundings
 
 
-def getrf(A, fmt_f, nb=None, trailing="fma32"):
+def getrf(A, fmt_f, nb=None, trailing="fma32", native=None):
     """Factor A (float64, values representable in fmt_f).
 
     Returns (W, piv, info): W holds the unit lower triangle of L below the
     diagonal and U on and above it, all entries representable in fmt_f.
+    native: True / False forces the C or the Python loops; None chooses C from
+    order NATIVE_MIN_N on when it is built (the two agree bit for bit).
     """
     A = np.asarray(A, dtype=np.float64)
     n = A.shape[0]
     if nb is None:
         nb = nb_auto(n, fmt_f)
+    same_steps = trailing == "fma32" or arith_format(fmt_f) == "fp64"
+    if native is None:
+        native = same_steps and n >= NATIVE_MIN_N and _native.available()
+    if native:
+        if not same_steps:
+            raise ValueError("the C loops implement the fma32 trailing chain (and float64 arithmetic) only")
+        return _native.getrf(A, fmt_f, nb)
     W = np.array(A, dtype=np.float64, order="F", copy=True)
     piv = np.arange(n, dtype=np.int64)
     info = 0
@@ -115,6 +132,11 @@ def getrf(A, fmt_f, nb=None, trailing="fma32"):
                     for k in range(jb):
                         acc = fma32(-L21[:, k:k + 1], U12[k:k + 1, :], acc)
                     W[j0 + jb:, j0 + jb:] = round_to(acc, fmt_f)
+                elif wa == "fp64":
+                    acc = np.zeros_like(W[j0 + jb:, j0 + jb:])
+                    for k in range(jb):
+                        acc = acc + L21[:, k:k + 1] * U12[k:k + 1, :]
+                    W[j0 + jb:, j0 + jb:] = W[j0 + jb:, j0 + jb:] - acc
                 else:
                     W[j0 + jb:, j0 + jb:] = round_to(rnd(W[j0 + jb:, j0 + jb:] - L21 @ U12), fmt_f)
     return W, piv, info

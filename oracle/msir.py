@@ -112,6 +112,19 @@ class Result:
     final: tuple = ()
 
 
+class _LoggedList(list):
+    """The history list; hands each appended step to ``log`` when one is given."""
+
+    def __init__(self, log):
+        super().__init__()
+        self._log = log
+
+    def append(self, step):
+        super().append(step)
+        if self._log is not None:
+            self._log(step)
+
+
 def next_uf(uf):
     """Next factorization format with unit roundoff <= u_f^2 (fp16/bf16 -> fp32 -> fp64)."""
     target = F.u(uf) ** 2
@@ -167,12 +180,14 @@ def render(history):
     return "; ".join(parts)
 
 
-def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None):
+def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None, log=None):
     """Run Alg. 4 on A x = b.
 
     ``correction``: optional callable (stage, rhat, uf, u) -> (d, k) replacing the
     SIR / GMRES correction solvers (used to drive the controller with scripted
     sequences in tests); d is returned already in precision u.
+    ``log``: optional callable receiving each history Step once it is complete
+    (progress of long runs; it does not affect the computation).
     """
     A = np.asarray(A, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
@@ -185,7 +200,7 @@ def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None):
     normA = float(np.abs(A).sum(axis=1).max())
     normb = float(np.abs(b).max())
     sqn = math.sqrt(n)
-    hist = []
+    hist = _LoggedList(log)
     level = 0
     n_lu = 1
 
@@ -336,7 +351,7 @@ def msir(A, b, params=Params(), x_true=None, return_x0=False, correction=None):
                 n_lu += 1
                 ev_pending = EV_SCALED if scal is not None else 0
                 alg = SIR
-    res = Result(x=x, cged=cged, status=status, history=hist, n_lu=n_lu)
+    res = Result(x=x, cged=cged, status=status, history=list(hist), n_lu=n_lu)
     rr = ops.residual(A, x, b, "dd")
     res.nbe = float(ops.rnorm_inf(rr) / (normA * float(np.abs(x).max()) + normb)) if np.any(x) else math.nan
     if x_true is not None:

@@ -1,14 +1,21 @@
-"""Writes the stored oracle results used by the full-size GPU parity test.
+"""Writes the stored oracle results used by the full-size GPU parity tests.
 
-Runs the CPU oracle (Alg. 4 with the readings of the oracle package) on the
-n = 4096 multistage workload (randsvd, kappa_2 = 1e6, geometric singular
-values; factors fp16 with column scaling, working precision fp32, residual
-fp64, GMRES tolerance 1e-4, restart 50, k_max = 0.1 n) and stores the stage
-history, the error figures and a fixed sample of the solution.  Only the
-oracle and the seeded input generator are called.  About 20-40 minutes on 8
-CPU cores.
+Runs the CPU oracle (Alg. 4 with the readings of the oracle package) on a configured
+workload at its full order and stores the stage history (level, variant, counted,
+GMRES iterations), the event bits, the error figures and a fixed sample of the
+solution.  Only the oracle and the seeded input generator are called.
 
-    python tests/golden/make_golden.py [config_id]
+    python tests/golden/make_golden.py 2            # n = 4096 multistage workload
+    python tests/golden/make_golden.py 3 fp16       # n = 8192 double-double workload,
+    python tests/golden/make_golden.py 3 bf16       #   with fp16 or bf16 factors
+
+Config 2: randsvd kappa_2 = 1e6, geometric singular values; fp16 factors with column
+scaling, working precision fp32, residual fp64, GMRES tolerance 1e-4, restart 50,
+k_max = 0.1 n.  Config 3: randsvd kappa_2 = 1e10, one small singular value; fp16 or
+bf16 factors (fp16 with the automatic scaling retry), working precision fp64,
+double-double residual, GMRES tolerance 1e-10, k_max = 0.1 n.  The LU runs as the
+oracle's C loops when they are built (python -m oracle.native.build).  Each step is
+printed as it completes.
 """
 import json
 import os
@@ -26,27 +33,47 @@ from paper_2107_06200_amd import workloads as WL  # noqa: E402
 SAMPLE_STRIDE = 64
 
 
-def main(cid=2):
+def golden_name(cid, uf=None):
     cfg = WL.CONFIGS[cid]
-    A, x, b = WL.config_system(cid)
+    if uf is None or uf == cfg["params"]["uf"] and cid == 2:
+        return "%s_oracle.json" % cfg["name"]
+    return "%s_%s_oracle.json" % (cfg["name"], uf)
+
+
+def main(cid=2, uf=None):
+    cfg = WL.CONFIGS[cid]
+    params = dict(cfg["params"])
+    if uf is not None:
+        params["uf"] = uf
     t = time.perf_counter()
-    ref = OM.msir(A, b, OM.Params(**cfg["params"]), x_true=x)
+    A, x, b = WL.config_system(cid)
+    print("input built in %.0f s" % (time.perf_counter() - t), flush=True)
+    t = time.perf_counter()
+
+    def log(step):
+        print("%7.0f s  level %d uf %s stage %d iter %d k %d z %.3e nbe %.3e events %d" % (
+            time.perf_counter() - t, step.level, step.uf, step.stage, step.iter, step.k, step.z, step.nbe,
+            step.events), flush=True)
+
+    ref = OM.msir(A, b, OM.Params(**params), x_true=x, log=log)
     dt = time.perf_counter() - t
     out = {
         "workload": cfg["name"], "n": cfg["n"], "kappa": cfg["kappa"], "mode": cfg["mode"],
-        "params": cfg["params"],
+        "params": params,
         "source": "oracle.msir.msir (Alg. 4), oracle run of %.0f s" % dt,
         "history": [[s.level, s.stage, int(s.counted), int(s.k)] for s in ref.history],
+        "events": [int(s.events) for s in ref.history],
+        "uf": [s.uf for s in ref.history],
         "render": OM.render(ref.history),
-        "cged": bool(ref.cged), "nbe": float(ref.nbe), "ferr": float(ref.ferr),
+        "cged": bool(ref.cged), "nbe": float(ref.nbe), "ferr": float(ref.ferr), "n_lu": int(ref.n_lu),
         "sample_stride": SAMPLE_STRIDE,
         "x_sample": [float(v) for v in ref.x[::SAMPLE_STRIDE]],
     }
-    path = os.path.join(HERE, "%s_oracle.json" % cfg["name"])
+    path = os.path.join(HERE, golden_name(cid, uf))
     with open(path, "w") as f:
         json.dump(out, f, indent=1)
-    print(path, out["render"], out["nbe"], "%.0f s" % dt)
+    print(path, out["render"], out["nbe"], "%.0f s" % dt, flush=True)
 
 
 if __name__ == "__main__":
-    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2)
+    main(int(sys.argv[1]) if len(sys.argv) > 1 else 2, sys.argv[2] if len(sys.argv) > 2 else None)
