@@ -216,13 +216,26 @@ MSIR_API int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA,
                      const msir_params* params, msir_result* outs, msir_step* hist, int hist_cap,
                      int* hist_len);
 
-/* Independent systems of uneven sizes solved with one handle: system i has order
- * n[i], matrix dA[i] (lda[i]), right-hand side db[i] and solution dx[i].  Host
- * arrays of device pointers.  outs: NULL or count results.  Returns the worst
- * status.                                                                        */
+/* Independent systems of uneven orders, Alg. 4 for each (the same controller,
+ * parameters and results as msir_solve): system i has order n[i], matrix dA[i]
+ * (lda[i]), right-hand side db[i], solution dx[i] and, when dxt is not NULL and
+ * dxt[i] is not NULL, exact solution dxt[i] (host arrays of device pointers).
+ * Systems of order <= 1024 run on batched kernels: one persistent launch factors all
+ * of them (one workgroup per system, largest first), one persistent launch runs the
+ * whole refinement of every system on the device (one workgroup per system, no host
+ * round trip per step); systems that raise u_f are factored at the new level in one
+ * more batched launch and resumed.  Their triangular solves (SIR and the GMRES
+ * operator) are substitutions in the operator precision.  Larger systems are solved
+ * one after another as by msir_solve.  outs: NULL or count results.  hist: NULL or a
+ * host array of count * hist_cap steps (system i from hist + i * hist_cap); hist_len:
+ * NULL or count lengths.  Returns the worst status, or an error: -3 a NULL array or
+ * pointer, lda[i] < n[i]; -8 CONV_TRUE without dxt[i]; -9 invalid params (also
+ * k_max above 256 for a system of order <= 1024); -12 hist_cap < 0; MSIR_ERR_SIZE an
+ * order outside [1, MSIR_MAX_N].                                                 */
 MSIR_API int msir_solve_batched(msir_handle* h, int count, const int* n, const double* const* dA,
                        const int* lda, const double* const* db, double* const* dx,
-                       const msir_params* params, msir_result* outs);
+                       const double* const* dxt, const msir_params* params, msir_result* outs,
+                       msir_step* hist, int hist_cap, int* hist_len);
 
 /* ---- Steps of the hot path (each call is one row of Algorithm 4) -------------
  * These are the building blocks msir_solve runs, exposed so each can be checked

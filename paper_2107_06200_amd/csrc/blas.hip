@@ -52,13 +52,6 @@ int convert(Ctx& c, int n, const double* A, int lda, int prec, const double* R, 
 }
 
 // ------------------------------------------------------------------ scaling
-// Power of two 2^-e with 2^(e-1) <= m < 2^e; 1 for m == 0 or non-finite m.
-__device__ __forceinline__ double pow2_equilibrator(double m) {
-  if (!(m > 0.0) || !__builtin_isfinite(m)) return 1.0;
-  int e;
-  (void)frexp(m, &e);
-  return ldexp(1.0, -e);
-}
 
 // row maxima of |A| (rows == 1) -> R, else R = 1
 __global__ __launch_bounds__(256) void k_rowmax(int n, const double* __restrict__ A, int lda, int rows,

@@ -106,6 +106,15 @@ __device__ __forceinline__ double round_to(double x, int p) {
   }
 }
 
+// Power of two 2^-e with 2^(e-1) <= m < 2^e; 1 for m == 0 or non-finite m (the
+// equilibration factors of Sec. 2.1.2).
+__device__ __forceinline__ double pow2_equilibrator(double m) {
+  if (!(m > 0.0) || !__builtin_isfinite(m)) return 1.0;
+  int e;
+  (void)frexp(m, &e);
+  return ldexp(1.0, -e);
+}
+
 // ---------------------------------------------------------------- storage traits
 // Storage of a factor matrix in format P.
 template <int P> struct Store;

@@ -820,6 +820,238 @@ static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info, bool 
   return 0;
 }
 
+// ------------------------------------------------------------------ batched factorization
+// One workgroup of PNT threads factors one system (order <= PNT: one panel row per
+// thread) at a time, taking systems from a queue (persistent grid): the Sec. 2.1.2
+// scaling, conversion to u_f, then per panel the same three steps as above with the
+// same arithmetic (panel_body; interchanges; U12 by the forward substitution of
+// k_swap_trsm; the trailing update by gemm_tile), so the factors equal those of the
+// single-system path with the same panel width bit for bit; the finiteness check with
+// the scaled retry; the permutation and the reciprocals of U's diagonal.
+//
+// Interchanges: wave w takes columns w, w + PNW, ...; lane k holds row j0 + k of the
+// column (one coalesced access), the new value of block row k is either another block
+// row (a lane move) or an outside row (one load per lane), and the outside rows that
+// change receive original block values (lane moves), as in k_swap_trsm_v.
+template <typename T>
+__device__ __forceinline__ T shfl_any(T v, int src) {
+  if constexpr (sizeof(T) == 8) return __shfl(v, src, 64);
+  else if constexpr (sizeof(T) == 4) return __shfl(v, src, 64);
+  else return (T)__shfl((int)v, src, 64);
+}
+
+template <int P, int NB, bool MF>
+__global__ __launch_bounds__(PNT) void k_bgetrf(BatchSys* __restrict__ sys, const int* __restrict__ list, int count,
+                                                int* __restrict__ queue, int slot, int scale_mode) {
+  typedef typename Store<P>::T ST;
+  typedef typename Arith<P>::T AT;
+  constexpr int TPP = fuse_fits<P, NB>() ? PNT / GNT : 2;   // 64 x 64 tiles per pass
+  __shared__ ST sA[TPP][GT][NB + 4], sB[TPP][GT][NB + 4];
+  __shared__ AT sL[NB][NB + 1];
+  __shared__ int s_src[NB], s_odst[NB], s_osrc[NB];
+  __shared__ int s_q, s_nout, s_bad;
+  __shared__ double sred[PNW];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  constexpr double theta = 0.0625;
+  const double xmax = P == P_FP16 ? 65504.0 : (P == P_BF16 ? 3.3895313892515355e38 : 3.4028234663852886e38);
+  for (;;) {
+    if (tid == 0) s_q = atomicAdd(queue, 1);
+    __syncthreads();
+    const int q = s_q;
+    __syncthreads();
+    if (q >= count) return;                     // uniform: every thread read the same q
+    BatchSys* sp = sys + list[q];
+    BatchFactor* F = &sp->f[slot];
+    const int n = sp->n, lda = sp->lda;
+    const double* A = sp->A;
+    ST* W = (ST*)F->W;
+    double* R = F->R;
+    double* Sc = F->S;
+    int* ipiv = F->ipiv;
+    bool use_scaling = P == P_FP16 && (scale_mode == MSIR_SCALE_ALWAYS || scale_mode == MSIR_SCALE_COLS);
+    bool rows = scale_mode != MSIR_SCALE_COLS;
+    double mu = 1.0;
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      mu = 1.0;
+      if (use_scaling) {
+        // R: row maxima (thread = row), S: column maxima of |R A| (wave = column),
+        // mu from the largest entry of |R A S|
+        if (tid < n) {
+          double m = 0.0;
+          if (rows)
+            for (int j = 0; j < n; ++j) m = fmax(m, fabs(A[(size_t)j * lda + tid]));
+          R[tid] = rows ? pow2_equilibrator(m) : 1.0;
+        }
+        __syncthreads();
+        double cm = 0.0;
+        for (int j = wv; j < n; j += PNW) {
+          double m = 0.0;
+          for (int i = lane; i < n; i += 64) m = fmax(m, fabs(R[i] * A[(size_t)j * lda + i]));
+          m = wave_max(m);
+          const double sj = pow2_equilibrator(m);
+          if (lane == 0) Sc[j] = sj;
+          cm = fmax(cm, m * sj);
+        }
+        if (lane == 0) sred[wv] = cm;
+        __syncthreads();
+        double t = 0.0;
+        for (int w = 0; w < PNW; ++w) t = fmax(t, sred[w]);
+        if (t > 0.0 && __builtin_isfinite(t)) {
+          int e;
+          (void)frexp(theta * xmax / t, &e);
+          mu = ldexp(1.0, e - 1);
+        }
+      }
+      // W = fl_f(mu R A S) (or fl_f(A)), thread = row
+      if (tid < n) {
+        const double ri = use_scaling ? R[tid] : 1.0;
+        for (int j = 0; j < n; ++j) {
+          double a = A[(size_t)j * lda + tid];
+          if (use_scaling) a = (mu * (ri * a)) * Sc[j];
+          W[(size_t)j * n + tid] = Store<P>::from_d(a);
+        }
+      }
+      if (tid == 0) F->info = 0;
+      __syncthreads();
+      for (int j0 = 0; j0 < n; j0 += NB) {
+        const int jb = min(NB, n - j0);
+        const int j1 = j0 + jb;
+        panel_body<P, 1, NB>(W, n, n, j0, jb, ipiv, &F->info, F->moved);
+        __syncthreads();
+        if (n - jb == 0) break;
+        // the moved-row list: source of each block row, outside destinations
+        const int* mv = F->moved;
+        if (tid == 0) s_nout = 0;
+        if (tid < NB) s_src[tid] = j0 + tid;
+        __syncthreads();
+        const int cnt = min(mv[0], 2 * NB);
+        if (tid < cnt) {
+          const int d = mv[1 + 2 * tid], sr = mv[2 + 2 * tid];
+          if (d >= j0 && d < j1) s_src[d - j0] = sr;
+          else {
+            const int k = atomicAdd(&s_nout, 1);
+            if (k < NB) { s_odst[k] = d; s_osrc[k] = sr; }
+          }
+        }
+        for (int e = tid; e < NB * NB; e += PNT) {
+          const int i = e % NB, k = e / NB;
+          sL[i][k] = (i < jb && k < jb) ? to_a<P>(W[(size_t)(j0 + k) * n + j0 + i], AT(0)) : AT(0);
+        }
+        __syncthreads();
+        const int nout = min(s_nout, NB);
+        // interchanges on every column outside the panel (wave per column)
+        {
+          const int sr = lane < NB ? s_src[lane] : j0;
+          const bool from_out = lane < jb && sr >= j1;
+          const int od = lane < nout ? s_odst[lane] : 0, os = lane < nout ? s_osrc[lane] - j0 : 0;
+          for (int cc = wv; cc < n - jb; cc += PNW) {
+            const int col = cc < j0 ? cc : cc + jb;
+            ST* w = W + (size_t)col * n;
+            const ST blk = lane < jb ? w[j0 + lane] : ST(0);
+            const ST ext = from_out ? w[sr] : ST(0);
+            const ST nbv = shfl_any(blk, from_out ? lane : (sr - j0));
+            const ST ov = shfl_any(blk, os);
+            if (lane < nout) w[od] = ov;
+            if (lane < jb) w[j0 + lane] = from_out ? ext : nbv;
+          }
+        }
+        __syncthreads();
+        // U12 = L11^{-1} A12 (thread = column right of the panel; rows in increasing
+        // order, fused multiply-adds in the arithmetic format), rounded to u_f
+        if (tid < n - j1) {
+          ST* w = W + (size_t)(j1 + tid) * n;
+          AT u[NB];
+#pragma unroll
+          for (int k = 0; k < NB; ++k) u[k] = k < jb ? to_a<P>(w[j0 + k], AT(0)) : AT(0);
+#pragma unroll
+          for (int k = 1; k < NB; ++k) {
+            if (k < jb) {
+              AT acc = u[k];
+#pragma unroll
+              for (int i = 0; i < NB; ++i)
+                if (i < k) acc = a_fma(-sL[k][i], u[i], acc);
+              u[k] = acc;
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < NB; ++k)
+            if (k < jb) w[j0 + k] = from_a<P>(u[k]);
+        }
+        __syncthreads();
+        // trailing update, TPP tiles per pass (threads past TPP tiles keep the barriers)
+        const int mt = (n - j1 + GT - 1) / GT;
+        const int sub = tid / GNT;
+        for (int t0 = 0; t0 < mt * mt; t0 += TPP) {
+          if (sub < TPP) {
+            const int tile = t0 + sub;
+            const int bx = tile < mt * mt ? tile % mt : mt, by = tile < mt * mt ? tile / mt : mt;
+            gemm_tile<P, NB, MF>(W, n, n, j0, jb, bx, by, tid % GNT, sA[sub], sB[sub]);
+          } else {
+            __syncthreads();     // gemm_tile's staging barrier
+          }
+          __syncthreads();       // the tiles' LDS is reused by the next pass
+        }
+      }
+      // the Sec. 2.1.2 retry: unscaled fp16 factors holding Inf or NaN
+      if (P == P_FP16 && scale_mode == MSIR_SCALE_AUTO && !use_scaling) {
+        if (tid == 0) s_bad = 0;
+        __syncthreads();
+        int bad = 0;
+        if (tid < n)
+          for (int j = 0; j < n; ++j) bad |= !__builtin_isfinite(Store<P>::to_d(W[(size_t)j * n + tid]));
+        if (bad) s_bad = 1;
+        __syncthreads();
+        if (s_bad) { use_scaling = true; rows = true; continue; }
+      }
+      break;
+    }
+    // permutation from the interchanges (sequential, in LDS), reciprocals of U_ii
+    __shared__ int s_perm[kBatchMaxN];
+    if (tid < n) s_perm[tid] = tid;
+    __syncthreads();
+    if (tid == 0)
+      for (int j = 0; j < n; ++j) {
+        const int k = ipiv[j];
+        if (k != j) { const int t = s_perm[j]; s_perm[j] = s_perm[k]; s_perm[k] = t; }
+      }
+    __syncthreads();
+    if (tid < n) {
+      F->perm[tid] = s_perm[tid];
+      F->rinv[tid] = 1.0 / Store<P>::to_d(W[(size_t)tid * n + tid]);
+      if (!use_scaling) { R[tid] = 1.0; Sc[tid] = 1.0; }
+    }
+    if (tid == 0) {
+      F->mu = use_scaling ? mu : 1.0;
+      F->scaled = use_scaling ? 1 : 0;
+      F->valid = 1;
+      sp->st->n_lu += 1;
+    }
+    __syncthreads();
+  }
+}
+
+template <int P, int NB>
+static void launch_bgetrf(Ctx& c, BatchSys* sys, const int* list, int count, int* queue, int slot, int scale_mode,
+                          bool mf, int grid) {
+  if (mf) k_bgetrf<P, NB, true><<<grid, PNT, 0, c.stream>>>(sys, list, count, queue, slot, scale_mode);
+  else k_bgetrf<P, NB, false><<<grid, PNT, 0, c.stream>>>(sys, list, count, queue, slot, scale_mode);
+}
+
+int batch_getrf(Ctx& c, BatchSys* sys, const int* list, int count, int* queue, int slot, int scale_mode, int update,
+                int grid) {
+  if (count <= 0) return 0;
+  const bool mf = update == MSIR_LU_MFMA && slot != P_FP64;
+  switch (slot) {
+    case P_FP16: launch_bgetrf<P_FP16, 64>(c, sys, list, count, queue, slot, scale_mode, mf, grid); break;
+    case P_BF16: launch_bgetrf<P_BF16, 64>(c, sys, list, count, queue, slot, scale_mode, mf, grid); break;
+    case P_FP32: launch_bgetrf<P_FP32, 64>(c, sys, list, count, queue, slot, scale_mode, mf, grid); break;
+    case P_FP64: launch_bgetrf<P_FP64, 32>(c, sys, list, count, queue, slot, scale_mode, false, grid); break;
+    default: return -3;
+  }
+  HIP_CHECK(hipGetLastError());
+  return 0;
+}
+
 int nb_auto(int n, int prec) {
   const int R = (n + PNT - 1) / PNT;
   int nb = R <= 1 ? 64 : R <= 2 ? 32 : R <= 4 ? 16 : 8;

@@ -279,7 +279,8 @@ struct msir_handle {
   bool share = false;            // reuse valid slots instead of refactoring
   int factorizations = 0;        // factorizations performed (counter for the results)
   bool au_valid = false;         // Au holds fl32(A) of the cached A (share mode)
-  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Acsr;
+  DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Acsr, Bws;
+  int batch_grid_lu = 256, batch_grid_ref = 512;   // persistent workgroups of the batched launches
   double* dev_small = nullptr;   // device scalars
   double* host_small = nullptr;  // pinned host scalars
   std::vector<int> hpiv, hperm, hpinv;
@@ -463,6 +464,137 @@ static int solve_with(msir_handle* h, int n, int comp, const double* t_hi, const
   return trsv(h->c, a);
 }
 
+// ------------------------------------------------------------------ batched systems
+
+// Alg. 4 on the systems idx (orders <= kBatchMaxN) with the batched kernels: one
+// persistent launch factors every system at its current level (one workgroup per
+// system, largest first), one persistent launch runs the controller of every system
+// until it converges, stops or needs the next factor format; the systems that
+// escalate are factored at that level in another batched launch and resumed.
+static int batched_solve(msir_handle* h, const std::vector<int>& idx, const int* n, const double* const* dA,
+                         const int* lda, const double* const* db, double* const* dx, const double* const* dxt,
+                         const msir_params& P, msir_result* outs, msir_step* hist, int hist_cap, int* hist_len,
+                         int* worst) {
+  Ctx& c = h->c;
+  const int cnt = (int)idx.size();
+  const int hcap = std::max(hist_cap, 1);
+  // factor formats the ladder can reach from P.uf
+  bool reach[4] = {false, false, false, false};
+  for (int f = P.uf; f >= 0; f = next_uf(f)) reach[f] = true;
+  // workspace: one allocation, carved per system (256-byte aligned pieces)
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  std::vector<size_t> off(cnt + 1, 0);
+  for (int q = 0; q < cnt; ++q) {
+    const size_t m = (size_t)n[idx[q]];
+    const double km = P.k_max > 0 ? P.k_max : 0.1 * (double)m;
+    const size_t kc = (size_t)std::max(1.0, ceil(km));
+    size_t b = 0;
+    for (int f = 0; f < 4; ++f)
+      if (reach[f]) b += al(m * m * store_bytes(f)) + al(m * 3 * sizeof(double)) + al(m * 2 * sizeof(int)) +
+                         al(kBatchMoved * sizeof(int));
+    if (P.u == MSIR_FP32) b += al(m * m * sizeof(float));
+    b += al(m * kBatchVecs * sizeof(double));
+    b += al((kc + 1) * m * sizeof(double)) + al((kc + 1) * kc * sizeof(double));
+    b += al((size_t)hcap * sizeof(msir_step)) + al(sizeof(msir_result)) + al(sizeof(BatchState));
+    off[q + 1] = off[q] + b;
+  }
+  const size_t meta = al(cnt * sizeof(BatchSys)) + al(cnt * sizeof(int)) + 256;
+  char* base = (char*)c.grow(h->Bws, off[cnt] + meta);
+  if (!base) return MSIR_ERR_ALLOC;
+  BatchSys* dsys = (BatchSys*)(base + off[cnt]);
+  int* dlist = (int*)((char*)dsys + al(cnt * sizeof(BatchSys)));
+  int* dqueue = (int*)((char*)dlist + al(cnt * sizeof(int)));
+  std::vector<BatchSys> hs(cnt);
+  std::vector<BatchState> st(cnt);
+  for (int q = 0; q < cnt; ++q) {
+    const int i = idx[q];
+    const size_t m = (size_t)n[i];
+    const double km = P.k_max > 0 ? P.k_max : 0.1 * (double)m;
+    const int kc = std::max(1, (int)ceil(km));
+    char* p = base + off[q];
+    BatchSys& S = hs[q];
+    memset(&S, 0, sizeof(S));
+    S.n = n[i]; S.lda = lda[i]; S.A = dA[i]; S.b = db[i]; S.x = dx[i]; S.xt = dxt ? dxt[i] : nullptr;
+    for (int f = 0; f < 4; ++f) {
+      if (!reach[f]) continue;
+      BatchFactor& F = S.f[f];
+      F.W = p; p += al(m * m * store_bytes(f));
+      F.rinv = (double*)p; F.R = F.rinv + m; F.S = F.R + m; p += al(m * 3 * sizeof(double));
+      F.ipiv = (int*)p; F.perm = F.ipiv + m; p += al(m * 2 * sizeof(int));
+      F.moved = (int*)p; p += al(kBatchMoved * sizeof(int));
+      F.mu = 1.0;
+    }
+    if (P.u == MSIR_FP32) { S.Au = (float*)p; p += al(m * m * sizeof(float)); }
+    S.vec = (double*)p; p += al(m * kBatchVecs * sizeof(double));
+    S.kcap = kc;
+    S.V = (double*)p; p += al((size_t)(kc + 1) * m * sizeof(double));
+    S.H = (double*)p; p += al((size_t)(kc + 1) * kc * sizeof(double));
+    S.hist = (msir_step*)p; S.hist_cap = hist_cap; p += al((size_t)hcap * sizeof(msir_step));
+    S.res = (msir_result*)p; p += al(sizeof(msir_result));
+    S.st = (BatchState*)p;
+    BatchState& s0 = st[q];
+    memset(&s0, 0, sizeof(s0));
+    s0.phase = 0; s0.uf = P.uf; s0.u = P.u; s0.ur = P.ur; s0.ux = P.ux; s0.status = MSIR_NOT_CONVERGED;
+  }
+  HIP_CHECK(hipMemcpyAsync(dsys, hs.data(), cnt * sizeof(BatchSys), hipMemcpyHostToDevice, c.stream));
+  for (int q = 0; q < cnt; ++q)
+    HIP_CHECK(hipMemcpyAsync(hs[q].st, &st[q], sizeof(BatchState), hipMemcpyHostToDevice, c.stream));
+  // queue order: largest systems first
+  std::vector<int> all(cnt);
+  for (int q = 0; q < cnt; ++q) all[q] = q;
+  std::stable_sort(all.begin(), all.end(), [&](int a, int b) { return hs[a].n > hs[b].n; });
+  const int grid_f = std::min(cnt, h->batch_grid_lu);
+  const int grid_r = std::min(cnt, h->batch_grid_ref);
+  std::vector<int> pend_level(cnt, P.uf);   // level each system needs factored (-1: none)
+  std::vector<int> run;
+  for (int round = 0; round < 8; ++round) {
+    // factorizations, one batched launch per level
+    for (int f = 0; f < 4; ++f) {
+      std::vector<int> L;
+      for (int q : all)
+        if (pend_level[q] == f) L.push_back(q);
+      if (L.empty()) continue;
+      HIP_CHECK(hipMemcpyAsync(dlist, L.data(), L.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+      HIP_CHECK(hipMemsetAsync(dqueue, 0, sizeof(int), c.stream));
+      int rc = batch_getrf(c, dsys, dlist, (int)L.size(), dqueue, f, P.scaling, P.lu_update,
+                           std::min((int)L.size(), grid_f));
+      if (rc) return rc;
+    }
+    run.clear();
+    for (int q : all)
+      if (pend_level[q] >= 0) run.push_back(q);
+    if (run.empty()) break;
+    HIP_CHECK(hipMemcpyAsync(dlist, run.data(), run.size() * sizeof(int), hipMemcpyHostToDevice, c.stream));
+    HIP_CHECK(hipMemsetAsync(dqueue, 0, sizeof(int), c.stream));
+    int rc = batch_refine(c, dsys, dlist, (int)run.size(), dqueue, P, std::min((int)run.size(), grid_r));
+    if (rc) return rc;
+    for (int q : run)
+      HIP_CHECK(hipMemcpyAsync(&st[q], hs[q].st, sizeof(BatchState), hipMemcpyDeviceToHost, c.stream));
+    HIP_CHECK(hipStreamSynchronize(c.stream));
+    for (int q = 0; q < cnt; ++q) pend_level[q] = -1;
+    for (int q : run)
+      if (st[q].phase == 2) pend_level[q] = st[q].uf;
+  }
+  // results and histories
+  std::vector<msir_result> res(cnt);
+  for (int q = 0; q < cnt; ++q)
+    HIP_CHECK(hipMemcpyAsync(&res[q], hs[q].res, sizeof(msir_result), hipMemcpyDeviceToHost, c.stream));
+  if (hist && hist_cap > 0)
+    for (int q = 0; q < cnt; ++q)
+      HIP_CHECK(hipMemcpyAsync(hist + (size_t)idx[q] * hist_cap, hs[q].hist, (size_t)hist_cap * sizeof(msir_step),
+                               hipMemcpyDeviceToHost, c.stream));
+  HIP_CHECK(hipStreamSynchronize(c.stream));
+  for (int q = 0; q < cnt; ++q) {
+    const int i = idx[q];
+    if (st[q].phase != 3) res[q].status = MSIR_ERR_HIP;   // not finished: cannot happen
+    if (outs) outs[i] = res[q];
+    if (hist_len) hist_len[i] = st[q].hist_len;
+    if (res[q].status < 0) return res[q].status;
+    *worst = std::max(*worst, res[q].status);
+  }
+  return 0;
+}
+
 // ------------------------------------------------------------------ C ABI
 extern "C" {
 
@@ -539,7 +671,7 @@ int msir_destroy(msir_handle* h) {
   Ctx& c = h->c;
   DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.part_x, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
                     &c.tmp_scalar, &c.moved, &c.tr_part, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
-                    &h->tmp2, &h->Acsr};
+                    &h->tmp2, &h->Acsr, &h->Bws};
   for (DevBuf* b : bufs) c.release(b->p, b->bytes);
   for (FactorSlot& s : h->slot) {
     DevBuf* ib[] = {&s.Xd, &s.Yd, &s.Xf, &s.Yf};
@@ -1587,17 +1719,43 @@ int msir_solve_multi(msir_handle* h, int n, int nrhs, const double* dA, int lda,
 }
 
 int msir_solve_batched(msir_handle* h, int count, const int* n, const double* const* dA, const int* lda,
-                       const double* const* db, double* const* dx, const msir_params* params, msir_result* outs) {
+                       const double* const* db, double* const* dx, const double* const* dxt,
+                       const msir_params* params, msir_result* outs, msir_step* hist, int hist_cap,
+                       int* hist_len) {
   if (!h) return -1;
   if (count < 0) return -2;
+  if (count == 0) return 0;
   if (!n || !dA || !lda || !db || !dx) return -3;
+  if (hist_cap < 0) return -12;
+  msir_params P;
+  if (params) P = *params; else msir_params_default(&P);
+  for (int i = 0; i < count; ++i) {
+    if (n[i] < 1 || n[i] > MSIR_MAX_N) return MSIR_ERR_SIZE;
+    if (lda[i] < n[i] || !dA[i] || !db[i] || !dx[i]) return -3;
+    if (int e = check_params(n[i], P, dxt && dxt[i])) return e == -7 ? -8 : -9;
+    // the batched controller keeps the Givens rotations of at most 256 iterations
+    const double km = P.k_max > 0 ? P.k_max : 0.1 * n[i];
+    if (n[i] <= kBatchMaxN && ceil(km) > 256) return -9;
+  }
+  Ctx& c = h->c;
+  HIP_CHECK(hipSetDevice(c.device));
+  // systems above the batched kernels' order are solved one at a time
+  std::vector<int> small;
   int worst = 0;
   for (int i = 0; i < count; ++i) {
-    int rc = msir_solve(h, n[i], dA[i], lda[i], db[i], dx[i], nullptr, params, outs ? outs + i : nullptr, nullptr,
-                        0, nullptr);
+    if (n[i] <= kBatchMaxN) { small.push_back(i); continue; }
+    invalidate_factors(h);
+    std::vector<msir_step> H;
+    int rc = solve_one(h, n[i], dA[i], lda[i], db[i], dx[i], dxt ? dxt[i] : nullptr, P, outs ? outs + i : nullptr, H);
     if (rc < 0) return rc;
+    if (hist_len) hist_len[i] = (int)H.size();
+    if (hist && hist_cap > 0)
+      memcpy(hist + (size_t)i * hist_cap, H.data(), std::min((size_t)hist_cap, H.size()) * sizeof(msir_step));
     worst = std::max(worst, rc);
   }
+  if (small.empty()) return worst;
+  int rc = batched_solve(h, small, n, dA, lda, db, dx, dxt, P, outs, hist, hist_cap, hist_len, &worst);
+  if (rc < 0) return rc;
   return worst;
 }
 

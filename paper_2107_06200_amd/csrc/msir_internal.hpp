@@ -213,4 +213,60 @@ int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au
 int gather(Ctx& c, int n, const double* src, const int* idx, double* dst);
 size_t diag_inv_doubles(int n);
 
+// ---- batched independent systems (getrf.hip: factorization; batched.hip: Alg. 4) ----
+// Systems of order up to kBatchMaxN are solved by one workgroup each, taken from a
+// queue; the descriptors live in device memory and carry every pointer a system needs.
+constexpr int kBatchMaxN = 1024;
+constexpr int kBatchMoved = 2 * 64 * 2 + 4;   // moved-row list of one panel (ints)
+
+// One factorization level of a system (slot = factor format).
+struct BatchFactor {
+  void* W;            // n x n, ld n, in the slot's format
+  int* ipiv;          // n
+  int* perm;          // n: (P t)[i] = t[perm[i]]
+  double* rinv;       // n: 1 / U_ii
+  double* R;          // n: row scaling (1 when unscaled)
+  double* S;          // n: column scaling
+  int* moved;         // kBatchMoved
+  double mu;
+  int scaled, info, valid;
+};
+
+// Controller state of Alg. 4 for one system, kept in device memory between launches.
+struct BatchState {
+  int phase;          // 0 start, 1 refining, 2 needs a factorization at level uf, 3 done
+  int uf, u, ur, ux;
+  int level, alg, it, steps, gm_total, n_lu, hist_len, status, cged;
+  int have_phi0, cached, xa;    // xa: x lives in buffer 0 (1: buffer 1)
+  unsigned ev_pending;
+  double phi0, dprev, rho_max, xnorm, x0norm, normA, normb, s, s_true;
+};
+
+struct BatchSys {
+  int n, lda;
+  const double* A;
+  const double* b;
+  double* x;          // caller's solution vector
+  const double* xt;   // exact solution or null
+  BatchFactor f[4];   // fp16, bf16, fp32, fp64 levels
+  float* Au;          // fp32 copy of A (n x n, ld n) when u = fp32
+  double* vec;        // kBatchVecs vectors of n doubles (see batched.hip)
+  double* V;          // (kcap + 1) x n GMRES basis (u values)
+  double* H;          // (kcap + 1) x kcap Hessenberg columns
+  int kcap;           // ceil(k_max)
+  msir_step* hist;    // hist_cap steps (device)
+  int hist_cap;
+  msir_result* res;   // device result
+  BatchState* st;
+};
+constexpr int kBatchVecs = 16;
+
+// Factor the systems list[0..count) at level `slot` (Sec. 2.1.2 policy scale_mode) with
+// one persistent launch; `queue` is a zeroed device counter.
+int batch_getrf(Ctx& c, BatchSys* sys, const int* list, int count, int* queue, int slot, int scale_mode,
+                int update, int grid);
+// Alg. 4 for the systems list[0..count) from their saved states until each converges,
+// stops, or needs a factorization at a higher level (state phase 2).
+int batch_refine(Ctx& c, BatchSys* sys, const int* list, int count, int* queue, const msir_params& P, int grid);
+
 }  // namespace msir

@@ -76,8 +76,8 @@ _SIG = {
     "msir_solve_multi": (_I, [_P, _I, _I, _P, _I, _P, _I, _P, _I, _P, _I, ctypes.POINTER(Params),
                               ctypes.POINTER(Result), ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_solve_batched": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_P), ctypes.POINTER(_I),
-                                ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(Params),
-                                ctypes.POINTER(Result)]),
+                                ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(_P), ctypes.POINTER(Params),
+                                ctypes.POINTER(Result), ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_convert": (_I, [_P, _I, _P, _I, _I, _P, _P, _D, _P, _I]),
     "msir_scaling": (_I, [_P, _I, _P, _I, _I, _I, _P, _P, _P]),
     "msir_getrf": (_I, [_P, _I, _I, _P, _I, _I, _I, _P, ctypes.POINTER(_I)]),
@@ -268,19 +268,27 @@ def solve_multi(h, A, B, X_true=None, P=None, hist_cap=512, X=None):
     return X, [outs[i] for i in range(nrhs)], hists, rc
 
 
-def solve_batched(h, As, bs, P=None):
+def solve_batched(h, As, bs, x_true=None, P=None, hist_cap=256, xs=None):
+    """Alg. 4 for independent systems (As[i], bs[i]).  Returns
+    (xs, [Result per system], [[Step...] per system], worst status)."""
     count = len(As)
     As = [colmajor(A) for A in As]
-    xs = [torch.empty(A.shape[0], dtype=torch.float64, device=A.device) for A in As]
+    if xs is None:
+        xs = [torch.empty(A.shape[0], dtype=torch.float64, device=A.device) for A in As]
     ns = (ctypes.c_int * count)(*[A.shape[0] for A in As])
     ld = (ctypes.c_int * count)(*[_ld(A) for A in As])
     pA = (ctypes.c_void_p * count)(*[A.data_ptr() for A in As])
     pb = (ctypes.c_void_p * count)(*[b.data_ptr() for b in bs])
     px = (ctypes.c_void_p * count)(*[x.data_ptr() for x in xs])
+    pt = (ctypes.c_void_p * count)(*[t.data_ptr() for t in x_true]) if x_true is not None else None
     outs = (Result * count)()
-    rc = lib().msir_solve_batched(h.h, count, ns, pA, ld, pb, px, ctypes.byref(P) if P is not None else None, outs)
+    H = (Step * (hist_cap * count))()
+    hl = (ctypes.c_int * count)()
+    rc = lib().msir_solve_batched(h.h, count, ns, pA, ld, pb, px, pt, ctypes.byref(P) if P is not None else None,
+                                  outs, H, hist_cap, hl)
     _check(rc, "msir_solve_batched")
-    return xs, [outs[i] for i in range(count)], rc
+    hists = [[H[i * hist_cap + k] for k in range(min(hl[i], hist_cap))] for i in range(count)]
+    return xs, [outs[i] for i in range(count)], hists, rc
 
 
 def convert(h, A, fmt, R=None, S=None, mu=1.0):

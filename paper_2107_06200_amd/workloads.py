@@ -80,17 +80,36 @@ def config_system(cid, index=0, n=None):
     return randsvd(nn, c["kappa"], c["mode"], rng_for(cid, index))
 
 
-def batched_systems(count=512, nmin=64, nmax=1024, seed=4):
-    """Uneven batch: n log-uniform in [nmin, nmax], log10 kappa ~ U[1, 8], modes 2/3 alternating."""
+def batched_meta(count=512, nmin=64, nmax=1024, seed=4):
+    """Orders and conditioning of the uneven batch: n log-uniform in [nmin, nmax],
+    log10 kappa ~ U[1, 8], modes 2 (even index) and 3 (odd index)."""
     meta = rng_for(seed, 10 ** 6)
     out = []
     for i in range(count):
         n = int(round(math.exp(meta.uniform(math.log(nmin), math.log(nmax)))))
         kappa = 10.0 ** meta.uniform(1.0, 8.0)
-        mode = 2 if i % 2 == 0 else 3
-        A, x, b = randsvd(n, kappa, mode, rng_for(seed, i))
-        out.append(dict(n=n, kappa=kappa, mode=mode, A=A, x=x, b=b))
+        out.append(dict(index=i, n=n, kappa=kappa, mode=2 if i % 2 == 0 else 3))
     return out
+
+
+def batched_system(m, seed=4):
+    """(A, x_true, b) of one entry of batched_meta."""
+    return randsvd(m["n"], m["kappa"], m["mode"], rng_for(seed, m["index"]))
+
+
+def batched_systems(count=512, nmin=64, nmax=1024, seed=4):
+    """Uneven batch: n log-uniform in [nmin, nmax], log10 kappa ~ U[1, 8], modes 2/3 alternating."""
+    out = []
+    for m in batched_meta(count, nmin, nmax, seed):
+        A, x, b = batched_system(m, seed)
+        out.append(dict(m, A=A, x=x, b=b))
+    return out
+
+
+# Solver parameters of the uneven batch (fp16 factors, fp32 working precision, fp64
+# residual, GMRES tolerance 1e-6, k_max = 0.1 n by default).
+BATCHED_PARAMS = dict(uf="fp16", u="fp32", ur="fp64", ux="fp64", i_max=10, tau=1e-6, rho_thresh=0.5,
+                      k_max=None, restart=0, scaling="auto")
 
 
 def serving_requests(count=2000, sizes=(256, 512, 1024, 2048, 4096), seed=5, rate=1.0):

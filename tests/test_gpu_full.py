@@ -7,12 +7,16 @@ nbe <= 1e-15, and x on the stored sample of components within the tolerance of
 the solve tests.  The backward error is also recomputed on the host from the
 returned x with the oracle's double-double residual.
 
-n = 8192 (double-double residual, GMRES-IR): the oracle cannot run this size
-in a test, so properties that hold at any size are checked: convergence to
-nbe <= 1e-15 recomputed on the host (double-double residual), the forward
-error bound that backward error implies, and a well-formed stage history
-(levels only increase; within a level the variants follow SIR -> SGMRES-IR
--> GMRES-IR).
+n = 8192 (kappa 1e10, one small singular value, working precision fp64,
+double-double residual), with fp16 and with bf16 factors: compared the same way with
+the stored oracle results (tests/golden/gmresir_n8192_k1e10_mode2_{fp16,bf16}_oracle.json,
+written by make_golden.py from oracle/ only), with the fp32 fused multiply-add
+trailing update, whose factors are the oracle's bit for bit.  On this input neither
+format needs the GMRES-IR stage: fp16 goes SIR -> SGMRES-IR, bf16 too (its second
+SGMRES-IR call runs to the 820-iteration cap).  With the matrix-core update the run
+is checked for the oracle's outcome and properties that hold at any size:
+convergence to nbe <= 1e-15 recomputed on the host (double-double residual), the
+forward error bound that backward error implies, a well-formed stage history.
 """
 import json
 import os
@@ -87,9 +91,56 @@ def test_config2_full_size_vs_stored_oracle(M, h):
     assert np.abs(xg[::ref["sample_stride"]] - xs).max() <= tol * np.abs(xs).max()
 
 
-def test_config3_full_size_properties(M, h):
+@pytest.fixture(scope="module")
+def c3():
+    return WL.config_system(3)
+
+
+def compare_with_golden(M, hist, res, xg, A, b, ref, kappa, events=True):
+    g = blocks([(s.level, s.stage, s.counted, s.k_gmres) for s in hist])
+    o = blocks([tuple(t) for t in ref["history"]])
+    assert [bg[0] for bg in g] == [bo[0] for bo in o], (g, o)
+    for bg, bo in zip(g, o):
+        assert abs(bg[1] - bo[1]) <= 1, (g, o)
+        for kg, ko in zip(bg[2], bo[2]):
+            assert abs(kg - ko) <= 1, (g, o)
+    if events and "events" in ref:
+        # the event bits of each stage (union) as the oracle's
+        def union(seq, ev):
+            out, cur = [], None
+            for t, e in zip(seq, ev):
+                key = tuple(t[:3])
+                if cur is None or cur[0] != key:
+                    cur = [key, 0]
+                    out.append(cur)
+                cur[1] |= e
+            return [tuple(u) for u in out]
+        assert union([(s.level, s.stage, s.counted) for s in hist], [s.events for s in hist]) == \
+            union([t[:3] for t in ref["history"]], ref["events"])
+    assert res.status == 0 and res.cged == 1 and res.nbe <= 1e-15
+    assert OMET.nbe(A, xg, b) <= 1e-15                  # host double-double residual of the GPU's x
+    kinf = WL.kappa_inf(A)
+    tol = max(1e-12 * max(1.0, kappa * 1e-4), 4 * kinf * (res.nbe + ref["nbe"]))
+    xs = np.array(ref["x_sample"])
+    err = np.abs(xg[::ref["sample_stride"]] - xs).max() / np.abs(xs).max()
+    print("XERR sample err=%.3e literal=%.3e asserted=%.3e" % (err, 1e-12 * max(1.0, kappa * 1e-4), tol))
+    assert err <= tol
+
+
+@pytest.mark.parametrize("uf", ["fp16", "bf16"])
+def test_config3_full_size_vs_stored_oracle(M, h, c3, uf):
     cfg = WL.CONFIGS[3]
-    A, x, b = WL.config_system(3)
+    ref = json.load(open(os.path.join(GOLDEN, "%s_%s_oracle.json" % (cfg["name"], uf))))
+    A, x, b = c3
+    prm = dict(cfg["params"], uf=uf)
+    xg, res, hist, rc = solve(M, h, A, b, x, prm, lu_update="fma")
+    print("gpu", M.render(hist), "nbe %.2e" % res.nbe, "| stored oracle", ref["render"], "nbe %.2e" % ref["nbe"])
+    compare_with_golden(M, hist, res, xg, A, b, ref, cfg["kappa"])
+
+
+def test_config3_full_size_properties(M, h, c3):
+    cfg = WL.CONFIGS[3]
+    A, x, b = c3
     n = A.shape[0]
     xg, res, hist, rc = solve(M, h, A, b, x, cfg["params"])
     print("gpu", M.render(hist), "nbe %.2e" % res.nbe, "ferr %.2e" % res.ferr)

@@ -88,8 +88,8 @@ def blocks(seq):
 # two sides differ only in the float64 rounding of the residual and, in GMRES stages, in
 # the rounding of the preconditioned operator).  The first step of a stage measures the
 # current error of x: rtol MON_RTOL_FIRST.  Later SIR steps measure the contraction of
-# that error by the same u_f solve on both sides: rtol MON_RTOL_SIR while z >= MON_Z_FLOOR,
-# above the float64 noise of b - A x amplified by the correction solve.  Later GMRES-stage
+# that error by the same u_f solve on both sides: rtol MON_RTOL_SIR.  Both only while
+# z >= MON_Z_FLOOR, above the float64 noise of b - A x amplified by the correction solve.  Later GMRES-stage
 # steps measure the error left by a GMRES solve whose operator the GPU applies through
 # explicit inverses and the oracle by substitution; the two roundings leave different
 # remainders (observed up to a factor 1.5), so those are printed and the agreement of
@@ -168,9 +168,11 @@ def assert_same_history(hist, ref, monitors=True, lu_update="fma"):
                                                                     " ".join("%.1e" % d for d in dev)))
             if not fma:
                 continue
+            if ro[2] < MON_Z_FLOOR:
+                continue
             if i == 0:
                 rtol = MON_RTOL_FIRST
-            elif kg[1] == 0 and ro[2] >= MON_Z_FLOOR:
+            elif kg[1] == 0:
                 rtol = MON_RTOL_SIR
             else:
                 continue
@@ -237,6 +239,17 @@ def test_gmresir_dd_config3_shape(M, h, lu_update):
     # config 3 scaled down: mode 2, kappa 1e10, u = fp64, u_r = double-double
     A, x, b = WL.config_system(3, n=384)
     check(M, h, A, x, b, 1e10, lu_update=lu_update, name="config3_n384", **WL.CONFIGS[3]["params"])
+
+
+@pytest.mark.parametrize("kappa,levels", [(1e8, 2), (1e10, 3)])
+def test_gmresir_dd_stage_and_escalation(M, h, kappa, levels):
+    # the config-3 precisions (fp16 factors, fp64 working precision, double-double
+    # residual) on geometric singular values: SGMRES-IR and the GMRES-IR stage with the
+    # double-double operator both run to k_max, then u_f is raised (to fp32, and for
+    # kappa 1e10 on to fp64); reproducible update, history and x as the oracle's
+    A, x, b = WL.randsvd(200, kappa, 3, WL.rng_for(3, 200))
+    res, hist, ref = check(M, h, A, x, b, kappa, name="gmresir_dd_k%.0e" % kappa, **WL.CONFIGS[3]["params"])
+    assert any(s.stage == 2 for s in hist) and len({s.level for s in hist}) == levels
 
 
 @pytest.mark.parametrize("lu_update", UPDATES)
