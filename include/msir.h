@@ -87,10 +87,19 @@ typedef struct {
     int    lu_update;      /* trailing update of fp16/bf16/fp32 factors: MSIR_LU_MFMA
                               (matrix cores, default) or MSIR_LU_FMA (sequential fp32
                               fused multiply-adds, k ascending: reproducible)       */
+    int    gmres_op;       /* how GMRES applies U^{-1} L^{-1} in the operator precision
+                              p in {FP32, FP64} (single-system solves; p = DD always
+                              substitutes): MSIR_OP_INVERSE (default) multiplies by
+                              the explicit inverses of L and U, formed once per
+                              factorization in float64 and rounded to p;
+                              MSIR_OP_SUBST substitutes row by row in p as the
+                              method states (one dependent step per row)          */
 } msir_params;
 
 #define MSIR_LU_MFMA 0
 #define MSIR_LU_FMA  1
+#define MSIR_OP_INVERSE 0
+#define MSIR_OP_SUBST   1
 
 /* One refinement step (one residual + one correction), Alg. 4 loop body.       */
 typedef struct {

@@ -26,6 +26,9 @@ constexpr int BT = 256;                 // threads per workgroup
 constexpr int BW = BT / 64;             // waves
 constexpr int BR = kBatchMaxN / BT;     // rows per thread
 constexpr int BKMAX = 256;              // GMRES iterations per call at most
+constexpr int BCH = 16;                 // factor columns loaded per batch (diagonal blocks)
+constexpr int BCR = 8;                  // factor columns per batch for the rows off the block
+constexpr int BJ = 4;                   // matrix columns per batch in the products
 
 // vectors of a system (offsets in units of n doubles)
 enum BVec { V_XA = 0, V_XB = 1, V_X0 = 2, V_RHAT = 3, V_D = 4, V_T = 5, V_TLO = 6, V_Y = 7, V_YLO = 8,
@@ -92,14 +95,14 @@ __device__ __forceinline__ double bcast_d(double v, int l) {
 // ------------------------------------------------------------------ triangular solves
 // y = mu S U^{-1} L^{-1} P R t with every component rounded to comp (FP16..FP64), or in
 // double-double (comp == DD: t and y as hi/lo pairs, no rounding of components).
-template <int P>
+template <int P, bool DD>
 __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_hi, const double* t_lo, double* y_hi,
                         double* y_lo, BLds& L) {
   typedef typename Store<P>::T ST;
   typedef typename std::conditional<P == P_FP64, double, float>::type LT;   // factor values, exact
   const ST* W = (const ST*)F.W;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const bool dd = comp == P_DD;
+  constexpr bool dd = DD;
   const bool scaled = F.scaled != 0;
   // permuted, row-scaled right-hand side, rounded to comp
   for (int i = tid; i < n; i += BT) {
@@ -107,7 +110,7 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
     const double r = scaled ? F.R[pi] : 1.0;
     double h = t_hi[pi];
     if (scaled) h = r * h;
-    if (dd) {
+    if constexpr (DD) {
       double l = t_lo ? t_lo[pi] : 0.0;
       if (scaled) l = r * l;
       L.acc[i] = h;
@@ -123,52 +126,84 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
     if (wv == 0) {
       const int r = b0 + lane;
       double ah = r < n ? L.acc[r] : 0.0, al = (dd && r < n) ? L.alo[r] : 0.0;
-      LT lrc[64];
+      for (int k0 = 0; k0 < 64 && b0 + k0 < b1; k0 += BCH) {
+        LT lrc[BCH];
 #pragma unroll
-      for (int k = 0; k < 64; ++k) lrc[k] = (r < n && b0 + k < r) ? (LT)Store<P>::to_d(W[(size_t)(b0 + k) * n + r]) : LT(0);
+        for (int u = 0; u < BCH; ++u) {
+          const int c = b0 + k0 + u;
+          lrc[u] = (r < n && c < r) ? (LT)Store<P>::to_d(W[(size_t)c * n + r]) : LT(0);
+        }
 #pragma unroll
-      for (int k = 0; k < 64; ++k) {
-        const int c = b0 + k;
-        if (c < b1) {
-          double yh, yl = 0.0;
-          if (dd) { yh = bcast_d(ah, k); yl = bcast_d(al, k); }
-          else yh = bcast_d(round_to(ah, comp), k);
-          if (r > c && r < b1) {
-            if (dd) {
-              double ph, pl;
-              dd_mul_d(yh, yl, (double)lrc[k], ph, pl);
-              dd_add(ah, al, -ph, -pl, ah, al);
-            } else {
-              ah = __dsub_rn(ah, __dmul_rn((double)lrc[k], yh));
+        for (int u = 0; u < BCH; ++u) {
+          const int k = k0 + u, c = b0 + k;
+          if (c < b1) {
+            double yh, yl = 0.0;
+            if constexpr (DD) { yh = bcast_d(ah, k); yl = bcast_d(al, k); }
+            else yh = bcast_d(round_to(ah, comp), k);
+            if (r > c && r < b1) {
+              if constexpr (DD) {
+                double ph, pl;
+                dd_mul_d(yh, yl, (double)lrc[u], ph, pl);
+                dd_add(ah, al, -ph, -pl, ah, al);
+              } else {
+                ah = __dsub_rn(ah, __dmul_rn((double)lrc[u], yh));
+              }
             }
+            if (lane == k) { ah = yh; al = yl; }
           }
-          if (lane == k) { ah = yh; al = yl; }
         }
       }
       if (r < b1) { L.acc[r] = ah; if (dd) L.alo[r] = al; }
     }
     __syncthreads();
-    // rows below the block: columns b0..b1-1 in increasing order
-    for (int r = b1 + tid; r < n; r += BT) {
-      double ah = L.acc[r], al = dd ? L.alo[r] : 0.0;
-      ST lv[64];
+    // rows below the block: columns b0..b1-1 in increasing order; every row of the
+    // thread in the same pass, the next batch of factor entries loaded ahead
+    {
+      const int r0 = b1 + tid;
+      double ah[BR], al[BR];
 #pragma unroll
-      for (int k = 0; k < 64; ++k) lv[k] = W[(size_t)min(b0 + k, n - 1) * n + r];
+      for (int q = 0; q < BR; ++q) {
+        const int r = r0 + BT * q;
+        ah[q] = r < n ? L.acc[r] : 0.0;
+        al[q] = (dd && r < n) ? L.alo[r] : 0.0;
+      }
+      const int nq = r0 < n ? (n - r0 + BT - 1) / BT : 0;
+      if (nq > 0) {
+        for (int k0 = 0; k0 < 64 && b0 + k0 < b1; k0 += BCR) {
+          ST lv[BCR][BR];
 #pragma unroll
-      for (int k = 0; k < 64; ++k) {
-        if (b0 + k < b1) {
-          const double l = Store<P>::to_d(lv[k]);
-          if (dd) {
-            double ph, pl;
-            dd_mul_d(L.acc[b0 + k], L.alo[b0 + k], l, ph, pl);
-            dd_add(ah, al, -ph, -pl, ah, al);
-          } else {
-            ah = __dsub_rn(ah, __dmul_rn(l, L.acc[b0 + k]));
+          for (int u = 0; u < BCR; ++u) {
+            const size_t col = (size_t)min(b0 + k0 + u, n - 1) * n;
+#pragma unroll
+            for (int q = 0; q < BR; ++q)
+              if (q < nq) lv[u][q] = W[col + min(r0 + BT * q, n - 1)];
+          }
+#pragma unroll
+          for (int u = 0; u < BCR; ++u) {
+            const int c = b0 + k0 + u;
+            if (c < b1) {
+              const double yc = L.acc[c], ycl = dd ? L.alo[c] : 0.0;
+#pragma unroll
+              for (int q = 0; q < BR; ++q)
+                if (q < nq) {
+                  const double l = Store<P>::to_d(lv[u][q]);
+                  if constexpr (DD) {
+                    double ph, pl;
+                    dd_mul_d(yc, ycl, l, ph, pl);
+                    dd_add(ah[q], al[q], -ph, -pl, ah[q], al[q]);
+                  } else {
+                    ah[q] = __dsub_rn(ah[q], __dmul_rn(l, yc));
+                  }
+                }
+            }
           }
         }
+#pragma unroll
+        for (int q = 0; q < BR; ++q) {
+          const int r = r0 + BT * q;
+          if (q < nq && r < n) { L.acc[r] = ah[q]; if (dd) L.alo[r] = al[q]; }
+        }
       }
-      L.acc[r] = ah;
-      if (dd) L.alo[r] = al;
     }
     __syncthreads();
   }
@@ -179,59 +214,93 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
     if (wv == 0) {
       const int r = b0 + lane;
       double ah = r < n ? L.acc[r] : 0.0, al = (dd && r < n) ? L.alo[r] : 0.0;
-      LT urc[64];
-#pragma unroll
-      for (int k = 0; k < 64; ++k) urc[k] = (r < n && b0 + k < n) ? (LT)Store<P>::to_d(W[(size_t)(b0 + k) * n + r]) : LT(1);
       const double rin = r < n ? F.rinv[r] : 1.0;
+      const double udiag = r < n ? Store<P>::to_d(W[(size_t)r * n + r]) : 1.0;
+      for (int k0 = 64 - BCH; k0 >= 0; k0 -= BCH) {
+        if (b0 + k0 >= b1) continue;
+        LT urc[BCH];
 #pragma unroll
-      for (int k = 63; k >= 0; --k) {
-        const int c = b0 + k;
-        if (c < b1) {
-          double xh, xl = 0.0;
-          if (dd) {
-            double qh, ql;
-            dd_div_d(ah, al, (double)urc[k], qh, ql);   // lane k: U_cc at its own row
-            xh = bcast_d(qh, k);
-            xl = bcast_d(ql, k);
-          } else {
-            xh = bcast_d(round_to(__dmul_rn(ah, rin), comp), k);
-          }
-          if (r < c) {
-            if (dd) {
-              double ph, pl;
-              dd_mul_d(xh, xl, (double)urc[k], ph, pl);
-              dd_add(ah, al, -ph, -pl, ah, al);
+        for (int u = 0; u < BCH; ++u) {
+          const int c = b0 + k0 + u;
+          urc[u] = (r < n && c < n) ? (LT)Store<P>::to_d(W[(size_t)c * n + r]) : LT(0);
+        }
+#pragma unroll
+        for (int u = BCH - 1; u >= 0; --u) {
+          const int k = k0 + u, c = b0 + k;
+          if (c < b1) {
+            double xh, xl = 0.0;
+            if constexpr (DD) {
+              double qh, ql;
+              dd_div_d(ah, al, udiag, qh, ql);   // lane k: U_cc at its own row
+              xh = bcast_d(qh, k);
+              xl = bcast_d(ql, k);
             } else {
-              ah = __dsub_rn(ah, __dmul_rn((double)urc[k], xh));
+              xh = bcast_d(round_to(__dmul_rn(ah, rin), comp), k);
             }
+            if (r < c) {
+              if constexpr (DD) {
+                double ph, pl;
+                dd_mul_d(xh, xl, (double)urc[u], ph, pl);
+                dd_add(ah, al, -ph, -pl, ah, al);
+              } else {
+                ah = __dsub_rn(ah, __dmul_rn((double)urc[u], xh));
+              }
+            }
+            if (lane == k) { ah = xh; al = xl; }
           }
-          if (lane == k) { ah = xh; al = xl; }
         }
       }
       if (r < b1) { L.acc[r] = ah; if (dd) L.alo[r] = al; }
     }
     __syncthreads();
-    // rows above the block: columns b1-1 .. b0 in decreasing order
-    for (int r = tid; r < b0; r += BT) {
-      double ah = L.acc[r], al = dd ? L.alo[r] : 0.0;
-      ST uv[64];
+    // rows above the block: columns b1-1 .. b0 in decreasing order, every row of the
+    // thread in the same pass, the next batch loaded ahead
+    {
+      double ah[BR], al[BR];
 #pragma unroll
-      for (int k = 0; k < 64; ++k) uv[k] = W[(size_t)min(b0 + k, n - 1) * n + r];
+      for (int q = 0; q < BR; ++q) {
+        const int r = tid + BT * q;
+        ah[q] = r < b0 ? L.acc[r] : 0.0;
+        al[q] = (dd && r < b0) ? L.alo[r] : 0.0;
+      }
+      const int nq = tid < b0 ? (b0 - tid + BT - 1) / BT : 0;
+      if (nq > 0) {
+        for (int k0 = 64 - BCR; k0 >= 0; k0 -= BCR) {
+          if (b0 + k0 >= b1) continue;
+          ST uv[BCR][BR];
 #pragma unroll
-      for (int k = 63; k >= 0; --k) {
-        if (b0 + k < b1) {
-          const double u = Store<P>::to_d(uv[k]);
-          if (dd) {
-            double ph, pl;
-            dd_mul_d(L.acc[b0 + k], L.alo[b0 + k], u, ph, pl);
-            dd_add(ah, al, -ph, -pl, ah, al);
-          } else {
-            ah = __dsub_rn(ah, __dmul_rn(u, L.acc[b0 + k]));
+          for (int u = 0; u < BCR; ++u) {
+            const size_t col = (size_t)min(b0 + k0 + u, n - 1) * n;
+#pragma unroll
+            for (int q = 0; q < BR; ++q)
+              if (q < nq) uv[u][q] = W[col + min(tid + BT * q, b0 - 1)];
+          }
+#pragma unroll
+          for (int u = BCR - 1; u >= 0; --u) {
+            const int c = b0 + k0 + u;
+            if (c < b1) {
+              const double xc = L.acc[c], xcl = dd ? L.alo[c] : 0.0;
+#pragma unroll
+              for (int q = 0; q < BR; ++q)
+                if (q < nq) {
+                  const double uu = Store<P>::to_d(uv[u][q]);
+                  if constexpr (DD) {
+                    double ph, pl;
+                    dd_mul_d(xc, xcl, uu, ph, pl);
+                    dd_add(ah[q], al[q], -ph, -pl, ah[q], al[q]);
+                  } else {
+                    ah[q] = __dsub_rn(ah[q], __dmul_rn(uu, xc));
+                  }
+                }
+            }
           }
         }
+#pragma unroll
+        for (int q = 0; q < BR; ++q) {
+          const int r = tid + BT * q;
+          if (q < nq && r < b0) { L.acc[r] = ah[q]; if (dd) L.alo[r] = al[q]; }
+        }
       }
-      L.acc[r] = ah;
-      if (dd) L.alo[r] = al;
     }
     __syncthreads();
   }
@@ -239,7 +308,7 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
     double h = L.acc[i];
     if (scaled) h = F.mu * (F.S[i] * h);
     y_hi[i] = h;
-    if (dd) {
+    if constexpr (DD) {
       double l = L.alo[i];
       if (scaled) l = F.mu * (F.S[i] * l);
       y_lo[i] = l;
@@ -250,11 +319,20 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
 
 __device__ void b_solve_any(int P, const BatchFactor& F, int n, int comp, const double* t_hi, const double* t_lo,
                             double* y_hi, double* y_lo, BLds& L) {
+  if (comp == P_DD) {
+    switch (P) {
+      case P_FP16: b_solve<P_FP16, true>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
+      case P_BF16: b_solve<P_BF16, true>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
+      case P_FP32: b_solve<P_FP32, true>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
+      default: b_solve<P_FP64, true>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
+    }
+    return;
+  }
   switch (P) {
-    case P_FP16: b_solve<P_FP16>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
-    case P_BF16: b_solve<P_BF16>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
-    case P_FP32: b_solve<P_FP32>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
-    default: b_solve<P_FP64>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
+    case P_FP16: b_solve<P_FP16, false>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
+    case P_BF16: b_solve<P_BF16, false>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
+    case P_FP32: b_solve<P_FP32, false>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
+    default: b_solve<P_FP64, false>(F, n, comp, t_hi, t_lo, y_hi, y_lo, L); break;
   }
 }
 
@@ -265,25 +343,78 @@ __device__ void b_matvec(const BatchSys& S, int p, const double* v, double* t_hi
   const int n = S.n, tid = threadIdx.x;
   for (int j = tid; j < n; j += BT) L.acc[j] = p == P_FP32 ? round_to(v[j], P_FP32) : v[j];
   __syncthreads();
-  for (int i = tid; i < n; i += BT) {
-    if (p == P_FP32) {
-      double s = 0.0;
-      for (int j = 0; j < n; ++j) s = __fma_rn((double)S.Au[(size_t)j * n + i], L.acc[j], s);
-      t_hi[i] = round_to(s, P_FP32);
-    } else if (p == P_FP64) {
-      double s = 0.0;
-      for (int j = 0; j < n; ++j) s = __fma_rn(S.A[(size_t)j * S.lda + i], L.acc[j], s);
-      t_hi[i] = s;
-    } else {
-      double h = 0.0, l = 0.0;
-      for (int j = 0; j < n; ++j) {
-        double ph, pl;
-        two_prod(S.A[(size_t)j * S.lda + i], L.acc[j], ph, pl);
-        dd_add(h, l, ph, pl, h, l);
+  // thread t: rows t + BT q, q < nq, all of them in one pass over the columns (BJ
+  // columns' loads in flight per row); each row's sum in increasing column order
+  const int nq = (n + BT - 1) / BT;
+  int rr[BR];
+#pragma unroll
+  for (int q = 0; q < BR; ++q) rr[q] = min(tid + BT * q, n - 1);
+  if (p == P_FP32) {
+    double s[BR] = {};
+    for (int j0 = 0; j0 < n; j0 += BJ) {
+      float a[BJ][BR];
+#pragma unroll
+      for (int u = 0; u < BJ; ++u) {
+        const size_t col = (size_t)min(j0 + u, n - 1) * n;
+#pragma unroll
+        for (int q = 0; q < BR; ++q) if (q < nq) a[u][q] = S.Au[col + rr[q]];
       }
-      t_hi[i] = h;
-      t_lo[i] = l;
+#pragma unroll
+      for (int u = 0; u < BJ; ++u)
+        if (j0 + u < n) {
+          const double vj = L.acc[j0 + u];
+#pragma unroll
+          for (int q = 0; q < BR; ++q) if (q < nq) s[q] = __fma_rn((double)a[u][q], vj, s[q]);
+        }
     }
+#pragma unroll
+    for (int q = 0; q < BR; ++q) if (tid + BT * q < n) t_hi[tid + BT * q] = round_to(s[q], P_FP32);
+  } else if (p == P_FP64) {
+    double s[BR] = {};
+    for (int j0 = 0; j0 < n; j0 += BJ) {
+      double a[BJ][BR];
+#pragma unroll
+      for (int u = 0; u < BJ; ++u) {
+        const size_t col = (size_t)min(j0 + u, n - 1) * S.lda;
+#pragma unroll
+        for (int q = 0; q < BR; ++q) if (q < nq) a[u][q] = S.A[col + rr[q]];
+      }
+#pragma unroll
+      for (int u = 0; u < BJ; ++u)
+        if (j0 + u < n) {
+          const double vj = L.acc[j0 + u];
+#pragma unroll
+          for (int q = 0; q < BR; ++q) if (q < nq) s[q] = __fma_rn(a[u][q], vj, s[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < BR; ++q) if (tid + BT * q < n) t_hi[tid + BT * q] = s[q];
+  } else {
+    double h[BR] = {}, l[BR] = {};
+    for (int j0 = 0; j0 < n; j0 += BJ) {
+      double a[BJ][BR];
+#pragma unroll
+      for (int u = 0; u < BJ; ++u) {
+        const size_t col = (size_t)min(j0 + u, n - 1) * S.lda;
+#pragma unroll
+        for (int q = 0; q < BR; ++q) if (q < nq) a[u][q] = S.A[col + rr[q]];
+      }
+#pragma unroll
+      for (int u = 0; u < BJ; ++u)
+        if (j0 + u < n) {
+          const double vj = L.acc[j0 + u];
+#pragma unroll
+          for (int q = 0; q < BR; ++q)
+            if (q < nq) {
+              double ph, pl;
+              two_prod(a[u][q], vj, ph, pl);
+              dd_add(h[q], l[q], ph, pl, h[q], l[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < BR; ++q)
+      if (tid + BT * q < n) { t_hi[tid + BT * q] = h[q]; t_lo[tid + BT * q] = l[q]; }
   }
   __syncthreads();
 }
@@ -299,16 +430,39 @@ __device__ void b_residual(const BatchSys& S, const double* x, int ur, int u, do
   double* rh = S.vec + (size_t)V_T * n;
   double* rl = S.vec + (size_t)V_TLO * n;
   double m = 0.0, mt = 0.0, cq = 0.0;
-  for (int i = tid; i < n; i += BT) {
-    double s64 = 0.0, h = S.b[i], l = 0.0, ab = 0.0;
-    for (int j = 0; j < n; ++j) {
-      const double a = S.A[(size_t)j * S.lda + i], xj = L.acc[j];
-      s64 = __fma_rn(a, xj, s64);
-      double ph, pl;
-      two_prod(a, xj, ph, pl);
-      dd_add(h, l, -ph, -pl, h, l);
-      if (cbe) ab = __fma_rn(fabs(a), fabs(xj), ab);
+  const int nq = (n + BT - 1) / BT;
+  double s64q[BR] = {}, hq[BR], lq[BR] = {}, abq[BR] = {};
+  int rr[BR];
+#pragma unroll
+  for (int q = 0; q < BR; ++q) { rr[q] = min(tid + BT * q, n - 1); hq[q] = S.b[rr[q]]; }
+  for (int j0 = 0; j0 < n; j0 += BJ) {
+    double a[BJ][BR];
+#pragma unroll
+    for (int u = 0; u < BJ; ++u) {
+      const size_t col = (size_t)min(j0 + u, n - 1) * S.lda;
+#pragma unroll
+      for (int q = 0; q < BR; ++q) if (q < nq) a[u][q] = S.A[col + rr[q]];
     }
+#pragma unroll
+    for (int u = 0; u < BJ; ++u)
+      if (j0 + u < n) {
+        const double xj = L.acc[j0 + u];
+#pragma unroll
+        for (int q = 0; q < BR; ++q)
+          if (q < nq) {
+            s64q[q] = __fma_rn(a[u][q], xj, s64q[q]);
+            double ph, pl;
+            two_prod(a[u][q], xj, ph, pl);
+            dd_add(hq[q], lq[q], -ph, -pl, hq[q], lq[q]);
+            if (cbe) abq[q] = __fma_rn(fabs(a[u][q]), fabs(xj), abq[q]);
+          }
+      }
+  }
+#pragma unroll
+  for (int q = 0; q < BR; ++q) {
+    const int i = tid + BT * q;
+    if (i >= n) continue;
+    const double s64 = s64q[q], h = hq[q], l = lq[q], ab = abq[q];
     const double r64 = __dsub_rn(S.b[i], s64);
     const double rt = __dadd_rn(h, l);
     if (ur == P_DD) { rh[i] = h; rl[i] = l; m = (m != m) ? m : ((fabs(rt) != fabs(rt)) ? fabs(rt) : fmax(m, fabs(rt))); }
@@ -422,20 +576,24 @@ __device__ int b_gmres(const BatchSys& S, const BatchFactor& F, int uf, int u, i
       double wr[BR];
 #pragma unroll
       for (int q = 0; q < BR; ++q) { const int i = tid + q * BT; wr[q] = i < n ? w[i] : 0.0; }
+      double vr[BR], vnx[BR];
+#pragma unroll
+      for (int q = 0; q < BR; ++q) { const int i = tid + q * BT; vr[q] = i < n ? S.V[i] : 0.0; }
       for (int i2 = 0; i2 <= j; ++i2) {
-        const double* vi = S.V + (size_t)i2 * n;
-        double vr[BR];
+        if (i2 < j) {   // the next basis vector's loads in flight during this reduction
+          const double* vi = S.V + (size_t)(i2 + 1) * n;
+#pragma unroll
+          for (int q = 0; q < BR; ++q) { const int i = tid + q * BT; vnx[q] = i < n ? vi[i] : 0.0; }
+        }
         double pd = 0.0;
 #pragma unroll
-        for (int q = 0; q < BR; ++q) {
-          const int i = tid + q * BT;
-          vr[q] = i < n ? vi[i] : 0.0;
-          pd = __fma_rn(vr[q], wr[q], pd);
-        }
+        for (int q = 0; q < BR; ++q) pd = __fma_rn(vr[q], wr[q], pd);
         const double h = bsum(pd, L);
         if (tid == 0) L.hcol[i2] = h;
 #pragma unroll
         for (int q = 0; q < BR; ++q) wr[q] = round_to(__dsub_rn(wr[q], __dmul_rn(h, vr[q])), u);
+#pragma unroll
+        for (int q = 0; q < BR; ++q) vr[q] = vnx[q];
       }
       double pn = 0.0;
 #pragma unroll
@@ -555,6 +713,7 @@ __device__ void b_push(const BatchSys& S, BatchState& st, const msir_step& rec) 
 // stays in step; thread 0 alone writes the state and the history.
 __device__ void b_run(BatchSys& S, const BParams& P, BLds& L) {
   const int n = S.n, tid = threadIdx.x;
+  const uint64_t t_start = __builtin_amdgcn_s_memrealtime();   // 100 MHz clock
   BatchState st = *S.st;                 // private copy in every thread, written back by thread 0
   __syncthreads();
   double* xbuf[2] = {S.vec + (size_t)V_XA * n, S.vec + (size_t)V_XB * n};
@@ -758,14 +917,20 @@ __device__ void b_run(BatchSys& S, const BParams& P, BLds& L) {
       r->n_lu = st.n_lu;
       r->gmres_iters = st.gm_total;
       r->final_uf = st.uf; r->final_u = st.u; r->final_ur = st.ur;
-      r->t_factor_ms = 0.0; r->t_refine_ms = 0.0;
+      r->t_factor_ms = 0.0;
     }
   }
-  if (tid == 0) *S.st = st;
+  if (tid == 0) {
+    // device time of this system's refinement (all launches), 100 MHz clock
+    const double ms = (double)(__builtin_amdgcn_s_memrealtime() - t_start) * 1e-5;
+    if (st.phase == 3) S.res->t_refine_ms = st.t_ms + ms;
+    else st.t_ms += ms;
+    *S.st = st;
+  }
   __syncthreads();
 }
 
-__global__ __launch_bounds__(BT) void k_brefine(BatchSys* __restrict__ sys, const int* __restrict__ list, int count,
+__global__ __launch_bounds__(BT, 2) void k_brefine(BatchSys* __restrict__ sys, const int* __restrict__ list, int count,
                                                 int* __restrict__ queue, BParams P) {
   __shared__ BLds L;
   __shared__ int s_q;

@@ -629,6 +629,7 @@ void msir_params_default(msir_params* p) {
   p->nb = 0;
   p->max_steps = 1000;
   p->lu_update = MSIR_LU_MFMA;
+  p->gmres_op = MSIR_OP_INVERSE;
 }
 
 int msir_nb_auto(int n, msir_prec fmt) { return nb_auto(n, (int)fmt); }
@@ -1006,6 +1007,7 @@ static int check_params(int n, const msir_params& P, bool have_xt) {
       if (!nb_ok(n, f, P.nb)) return -8;
   }
   if (P.lu_update != MSIR_LU_MFMA && P.lu_update != MSIR_LU_FMA) return -8;
+  if (P.gmres_op != MSIR_OP_INVERSE && P.gmres_op != MSIR_OP_SUBST) return -8;
   return 0;
 }
 
@@ -1202,7 +1204,7 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
       op.pinv = h->cur->f.pinv; op.Rp = h->cur->f.scaled ? h->cur->f.Rp : nullptr;
       op.Xinv = op.Yinv = nullptr;
       op.inv_prec = -1;
-      if (op.p != P_DD) {
+      if (op.p != P_DD && P.gmres_op == MSIR_OP_INVERSE) {
         rc = ensure_inverses(h, n, op.p, &op.Xinv, &op.Yinv);
         if (rc) return rc;
         op.inv_prec = op.p;
@@ -1402,7 +1404,7 @@ static int ir5_one(msir_handle* h, int n, const double* dA, int lda, const doubl
   op.pinv = h->cur->f.pinv; op.Rp = h->cur->f.scaled ? h->cur->f.Rp : nullptr;
   op.Xinv = op.Yinv = nullptr;
   op.inv_prec = -1;
-  if (up != P_DD) {
+  if (up != P_DD && P.gmres_op == MSIR_OP_INVERSE) {
     rc = ensure_inverses(h, n, up, &op.Xinv, &op.Yinv);
     if (rc) return rc;
     op.inv_prec = up;
@@ -1598,6 +1600,7 @@ int msir_gmres_ir5(msir_handle* h, int n, const double* dA, int lda, const doubl
   if (P.conv == MSIR_CONV_TRUE && !dxt) return -7;
   if (P.nb != 0 && !nb_ok(n, P.uf, P.nb)) return -8;
   if (P.lu_update != MSIR_LU_MFMA && P.lu_update != MSIR_LU_FMA) return -8;
+  if (P.gmres_op != MSIR_OP_INVERSE && P.gmres_op != MSIR_OP_SUBST) return -8;
   // u_g in {FP32, FP64} not more precise than u; u_p in {FP32, FP64, DD}
   if ((ug != MSIR_FP32 && ug != MSIR_FP64) || unit_roundoff(ug) < unit_roundoff(P.u)) return -9;
   if (up != MSIR_FP32 && up != MSIR_FP64 && up != MSIR_DD) return -9;

@@ -240,6 +240,7 @@ struct BatchState {
   int have_phi0, cached, xa;    // xa: x lives in buffer 0 (1: buffer 1)
   unsigned ev_pending;
   double phi0, dprev, rho_max, xnorm, x0norm, normA, normb, s, s_true;
+  double t_ms;        // refinement device time of the launches so far
 };
 
 struct BatchSys {

@@ -32,7 +32,7 @@ class Params(ctypes.Structure):
                 ("i_max", ctypes.c_int), ("tau", ctypes.c_double), ("rho_thresh", ctypes.c_double),
                 ("k_max", ctypes.c_double), ("restart", ctypes.c_int), ("conv", ctypes.c_int),
                 ("tol_nbe", ctypes.c_double), ("scaling", ctypes.c_int), ("nb", ctypes.c_int),
-                ("max_steps", ctypes.c_int), ("lu_update", ctypes.c_int)]
+                ("max_steps", ctypes.c_int), ("lu_update", ctypes.c_int), ("gmres_op", ctypes.c_int)]
 
 
 class Step(ctypes.Structure):
@@ -158,6 +158,8 @@ def params(**kw):
             v = SCALE[v]
         elif k == "lu_update" and isinstance(v, str):
             v = {"mfma": 0, "fma": 1}[v]
+        elif k == "gmres_op" and isinstance(v, str):
+            v = {"inverse": 0, "subst": 1}[v]
         setattr(P, k, v)
     return P
 
