@@ -246,6 +246,42 @@ MSIR_API int msir_solve_batched(msir_handle* h, int count, const int* n, const d
                        const double* const* dxt, const msir_params* params, msir_result* outs,
                        msir_step* hist, int hist_cap, int* hist_len);
 
+/* ---- Serving: requests admitted as slots and device memory free up ----------
+ * A server runs `slots` service slots, each a host thread with its own handle and
+ * HIP stream (default priority).  A request is one A with nrhs right-hand sides,
+ * solved by msir_solve_multi (Alg. 4 per column over one factor cache), with the
+ * server's parameters.  Requests start first come, first served as soon as a slot
+ * is free and the workspace estimate of the requests in service plus the new one
+ * fits hbm_budget_bytes (0: no cap; the first request always starts); requests in service run
+ * concurrently on their streams.  Slots keep their workspace between requests.
+ * All pointers of a request are device pointers owned by the caller and must stay
+ * valid until its completion has been returned by msir_server_poll.            */
+typedef struct msir_server msir_server;
+typedef struct {
+    int id;                 /* caller's tag, returned with the completion        */
+    int n, nrhs;
+    const double* dA; int lda;
+    const double* dB; int ldb;   /* n x nrhs right-hand sides                  */
+    double* dX; int ldx;         /* n x nrhs solutions (written)               */
+} msir_request;
+typedef struct {
+    int id, status;         /* status: worst msir_solve_multi status (or < 0)    */
+    int nrhs, slot, n_lu, gmres_iters;
+    double nbe_max;         /* largest final normwise backward error of the columns */
+    double t_submit_ms, t_start_ms, t_end_ms;   /* host clock since server creation */
+} msir_completion;
+/* -1 s NULL, -2 bad device, -3 slots outside [1, 64], MSIR_ERR_HIP / ERR_ALLOC.  */
+MSIR_API int msir_server_create(msir_server** s, int device, int slots, size_t hbm_budget_bytes,
+                                const msir_params* params);
+/* Queue a request (returns at once).  -2: invalid request fields.               */
+MSIR_API int msir_server_submit(msir_server* s, const msir_request* r);
+/* Move up to cap finished requests into out (*count of them), waiting up to
+ * wait_ms for the first one (0: no wait, < 0: until one finishes).  Returns the
+ * number of requests still queued, in service or finished and not yet returned. */
+MSIR_API int msir_server_poll(msir_server* s, msir_completion* out, int cap, int* count, int wait_ms);
+/* Stop: requests in service finish, queued ones are dropped; releases the slots. */
+MSIR_API int msir_server_destroy(msir_server* s);
+
 /* ---- Steps of the hot path (each call is one row of Algorithm 4) -------------
  * These are the building blocks msir_solve runs, exposed so each can be checked
  * on its own.  Matrices of format f are stored as: FP16/BF16 uint16 bit

@@ -52,16 +52,33 @@ class Result(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int), ("n", ctypes.c_int), ("nrhs", ctypes.c_int), ("dA", ctypes.c_void_p),
+                ("lda", ctypes.c_int), ("dB", ctypes.c_void_p), ("ldb", ctypes.c_int), ("dX", ctypes.c_void_p),
+                ("ldx", ctypes.c_int)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_int), ("status", ctypes.c_int), ("nrhs", ctypes.c_int), ("slot", ctypes.c_int),
+                ("n_lu", ctypes.c_int), ("gmres_iters", ctypes.c_int), ("nbe_max", ctypes.c_double),
+                ("t_submit_ms", ctypes.c_double), ("t_start_ms", ctypes.c_double), ("t_end_ms", ctypes.c_double)]
+
+
 SYMBOLS = ["msir_create", "msir_destroy", "msir_params_default", "msir_nb_auto", "msir_workspace_bytes",
            "msir_status_string", "msir_solve", "msir_solve_csr", "msir_gmres_ir5", "msir_solve_multi", "msir_solve_batched", "msir_convert",
            "msir_scaling", "msir_getrf", "msir_getrs", "msir_round", "msir_residual", "msir_residual_noalloc", "msir_gmres", "msir_backward_error",
-           "msir_timing", "msir_timing_get"]
+           "msir_timing", "msir_timing_get", "msir_server_create", "msir_server_submit", "msir_server_poll",
+           "msir_server_destroy"]
 
 _P = ctypes.c_void_p
 _I = ctypes.c_int
 _D = ctypes.c_double
 _SIG = {
     "msir_create": (_I, [ctypes.POINTER(_P), _I, ctypes.c_size_t, _P]),
+    "msir_server_create": (_I, [ctypes.POINTER(_P), _I, _I, ctypes.c_size_t, ctypes.POINTER(Params)]),
+    "msir_server_submit": (_I, [_P, ctypes.POINTER(Request)]),
+    "msir_server_poll": (_I, [_P, ctypes.POINTER(Completion), _I, ctypes.POINTER(_I), _I]),
+    "msir_server_destroy": (_I, [_P]),
     "msir_destroy": (_I, [_P]),
     "msir_params_default": (None, [ctypes.POINTER(Params)]),
     "msir_nb_auto": (_I, [_I, _I]),
@@ -128,14 +145,18 @@ def _ptr(t):
 
 
 def colmajor(A):
-    """Column-major (Fortran-order) version of a 2-D tensor (no copy if it already is)."""
-    if A.dim() == 2 and A.stride(0) == 1 and A.stride(1) >= max(1, A.shape[0]):
+    """Column-major (Fortran-order) version of a 2-D tensor (no copy if it already is;
+    a single column with unit row stride is column-major whatever its column stride)."""
+    if A.dim() == 2 and A.stride(0) == 1 and (A.shape[1] == 1 or A.stride(1) >= max(1, A.shape[0])):
         return A
-    return A.t().contiguous().t()
+    out = torch.empty_strided(tuple(A.shape), (1, max(1, A.shape[0])), dtype=A.dtype, device=A.device)
+    out.copy_(A)
+    return out
 
 
 def _ld(A):
-    return A.stride(1)
+    """Leading dimension of a column-major tensor (its rows for a single column)."""
+    return A.stride(1) if A.shape[1] > 1 else max(1, A.shape[0])
 
 
 def _prec(p):
@@ -412,6 +433,40 @@ def timing_get(h):
         _check(lib().msir_timing_get(h.h, i, ctypes.byref(c), ctypes.byref(t)), "msir_timing_get")
         out[name] = (c.value, t.value)
     return out
+
+
+class Server:
+    """msir_server: requests (A, B) solved concurrently in `slots` service slots under a
+    device-memory budget.  The caller keeps the tensors of a request alive until its
+    completion has been returned by poll()."""
+
+    def __init__(self, device=0, slots=4, budget=0, P=None):
+        self.s = ctypes.c_void_p()
+        _check(lib().msir_server_create(ctypes.byref(self.s), device, slots, budget,
+                                        ctypes.byref(P) if P is not None else None), "msir_server_create")
+        self.keep = {}
+
+    def submit(self, rid, A, B, X):
+        A, B, X = colmajor(A), colmajor(B), colmajor(X)
+        r = Request(rid, A.shape[0], B.shape[1], A.data_ptr(), _ld(A), B.data_ptr(), _ld(B), X.data_ptr(), _ld(X))
+        self.keep[rid] = (A, B, X)
+        _check(lib().msir_server_submit(self.s, ctypes.byref(r)), "msir_server_submit")
+
+    def poll(self, cap=64, wait_ms=0):
+        """(completions, outstanding)"""
+        out = (Completion * cap)()
+        cnt = ctypes.c_int(0)
+        rem = lib().msir_server_poll(self.s, out, cap, ctypes.byref(cnt), wait_ms)
+        _check(rem, "msir_server_poll")
+        comps = [out[i] for i in range(cnt.value)]
+        for c in comps:
+            self.keep.pop(c.id, None)
+        return comps, rem
+
+    def close(self):
+        if self.s:
+            lib().msir_server_destroy(self.s)
+            self.s = ctypes.c_void_p()
 
 
 def render(steps):
