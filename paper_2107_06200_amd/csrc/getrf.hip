@@ -21,13 +21,21 @@
 //     that take no part; each pivot row's U entries are saved in LDS when it is
 //     chosen.  The panel is written back to its final row positions, rounded to
 //     u_f.
-//  2. k_update (one workgroup per 32-column strip): applies the panel's row
-//     interchanges to the strip; for strips right of the panel it solves
-//     U12 = L11^{-1} A12 (forward substitution, fused multiply-adds, rows in
-//     increasing order, rounded to u_f) and subtracts L21 U12 from A22 on the
-//     matrix cores (fp16/bf16 MFMA 32x32x8 with fp32 accumulation; the result
-//     is rounded to u_f), or with fp32/fp64 fused multiply-adds for fp32/fp64
-//     factors.
+//  2. k_swap_trsm / k_swap_trsm_v (one wave per workgroup, one column per thread):
+//     every column outside the panel receives the panel's row interchanges (only
+//     the rows that move are touched, from the moved-row list the panel wrote);
+//     columns right of the panel then solve U12 = L11^{-1} A12 by forward
+//     substitution (fused multiply-adds in the arithmetic format, rows in
+//     increasing order, stored rounded to u_f).
+//  3. k_gemm (64 x 64 tiles of A22, 256 threads each): A22 -= L21 U12 with the
+//     panel's L21 and U12 staged in LDS.  For u_f in {fp16, bf16} either as an
+//     fp32 fused multiply-add chain in increasing k or on the matrix cores (MFMA
+//     32x32x8 f16/bf16 with fp32 accumulation); fp32 factors as an fp32 chain or
+//     MFMA 32x32x2 f32; fp64 as a float64 fused multiply-add chain.  The result is
+//     rounded to u_f.  Look-ahead (k_panel_gemm): the next panel, whose columns the
+//     previous update has finished, is factored by workgroup 0 of the launch that
+//     applies the rest of the trailing update.
+
 #include "common.hpp"
 #include "msir_internal.hpp"
 

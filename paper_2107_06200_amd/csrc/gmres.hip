@@ -1,18 +1,18 @@
 // Left-preconditioned GMRES for the correction equation (Alg. 2 GMRES-IR and
 // Alg. 3 SGMRES-IR), gfx950.
 //
-// Per iteration: w = fl_u(M^{-1} (A v_j)) with A v_j and the triangular solves
-// in the operator precision p (matvec + trsv launches), then k_arnoldi: one
-// workgroup of 1024 threads holds w in registers and runs modified
-// Gram-Schmidt against v_0..v_j (float64 inner products, each update
-// w <- fl_u(w - h v_i) with separately rounded multiply and subtract), the
-// norm, the Givens rotation update of the Hessenberg column and of the
-// residual vector g in float64, and the stopping test |g_{j+1}| <= tau beta0.
-// A device status word (done, iterations) makes every later launch of the
-// same cycle a no-op, so the host only synchronises every few iterations.
-// After a cycle: y = R^{-1} g by one wave, delta = fl_u(V y), d += delta; with a
-// restart length the preconditioned residual is updated as
-// fl_u(c - fl_u(M^{-1} A delta)).
+// Per iteration: w = fl_u(M^{-1} (A v_j)), the operator applied in precision p by
+// the caller's GmresOp (a matrix-vector product followed either by products with the
+// explicit inverses of the factors or by the two triangular substitutions), then
+// k_arnoldi: one workgroup (512 threads up to n = 4096, 1024 beyond) holds w in
+// registers and runs modified Gram-Schmidt against v_0..v_j (float64 inner products,
+// each update w <- fl_u(w - h v_i) with separately rounded multiply and subtract),
+// the norm, the Givens rotation update of the Hessenberg column and of the residual
+// vector g in float64, and the stopping test |g_{j+1}| <= tau beta0.  A device status
+// word (done, iterations) makes every later launch of the same cycle a no-op, so the
+// host only synchronises every few iterations.  After a cycle: y = R^{-1} g by one
+// wave, delta = fl_u(V y), d += delta; with a restart length the preconditioned
+// residual is updated as fl_u(c - fl_u(M^{-1} A delta)).
 #include "common.hpp"
 #include "msir_internal.hpp"
 #include "gmres.hpp"
