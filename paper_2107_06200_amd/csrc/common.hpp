@@ -229,30 +229,36 @@ __device__ __forceinline__ double dpp_d(double v) {
   const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, ROWMASK, 0xF, false);
   return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
-__device__ __forceinline__ double wave_sum_dpp(double v) {
+// The same sum left in lane 63 only (other lanes: partial or unspecified values), for
+// a caller that stores the total from that lane without a round trip through scalars.
+__device__ __forceinline__ double wave_sum_dpp_l63(double v) {
   v = __dadd_rn(v, dpp_d<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
   v = __dadd_rn(v, dpp_d<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
   v = __dadd_rn(v, dpp_d<0x141, 0xF>(v));   // row_half_mirror
   v = __dadd_rn(v, dpp_d<0x140, 0xF>(v));   // row_mirror
   v = __dadd_rn(v, dpp_d<0x142, 0xA>(v));   // row_bcast15 into rows 1, 3
   v = __dadd_rn(v, dpp_d<0x143, 0xC>(v));   // row_bcast31 into rows 2, 3
+  return v;
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v = wave_sum_dpp_l63(v);
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 63);
   const uint32_t hi = __builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
   return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
-// Sum of the W (8 or 16) per-wave partials p[0..W-1] (LDS), uniform over the calling
+// Sum of the W (4, 8 or 16) per-wave partials p[0..W-1] (LDS), uniform over the calling
 // wave: lane k < W reads p[k] and DPP steps fold them in a fixed order.  Only 8W bytes
 // of LDS are read per wave, instead of every lane reading all W values.
 template <int W>
 __device__ __forceinline__ double sum_lanes(const double* p) {
-  static_assert(W == 8 || W == 16, "8 or 16 partials");
+  static_assert(W == 4 || W == 8 || W == 16, "4, 8 or 16 partials");
   const int lane = threadIdx.x & 63;
   double v = lane < W ? p[lane] : 0.0;
   v = __dadd_rn(v, dpp_d<0xB1, 0xF>(v));    // quad_perm [1,0,3,2]
-  v = __dadd_rn(v, dpp_d<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]
-  v = __dadd_rn(v, dpp_d<0x141, 0xF>(v));   // row_half_mirror: lanes 0..7 hold the sum of 0..7
+  v = __dadd_rn(v, dpp_d<0x4E, 0xF>(v));    // quad_perm [2,3,0,1]: lanes 0..3 hold the sum of 0..3
+  if constexpr (W >= 8) v = __dadd_rn(v, dpp_d<0x141, 0xF>(v));   // row_half_mirror: lanes 0..7, sum of 0..7
   if constexpr (W == 16) v = __dadd_rn(v, dpp_d<0x140, 0xF>(v));   // row_mirror
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
   const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 0);

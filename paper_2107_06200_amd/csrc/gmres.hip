@@ -49,21 +49,17 @@ __global__ __launch_bounds__(GNT) void k_gmres_start(int n, const double* __rest
   }
 }
 
-// One modified Gram-Schmidt step against basis vector i held in B: h = <B, w> (one
-// barrier), w <- fl_u(w - h B).  h goes to the LDS copy of the Hessenberg column
-// (sHc, when the column fits) or straight to H (stored by every lane, same value,
-// so that all waves issue the same memory operations).
+// One modified Gram-Schmidt step against basis vector i held in B: returns
+// h = <B, w> (one barrier; uniform over the workgroup) after w <- fl_u(w - h B).
 template <int G, int U, int NT, bool TAIL, typename VT>
-__device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], const VT (&B)[G],
-                                         double* __restrict__ H, int ldh, double (*sh)[NT / 64], bool lds_col,
-                                         double* sHc) {
+__device__ __forceinline__ double mgs_step(int n, int i, double (&w)[G], const VT (&B)[G], double (*sh)[NT / 64]) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < G; ++t) acc = __fma_rn((double)B[t], w[t], acc);
-  acc = wave_sum_dpp(acc);
-  if (lane == 0) sh[i & 1][wv] = acc;
+  acc = wave_sum_dpp_l63(acc);
+  if (lane == 63) sh[i & 1][wv] = acc;
   __syncthreads();
   const double h = sum_lanes<NT / 64>(sh[i & 1]);
 #pragma unroll
@@ -71,11 +67,7 @@ __device__ __forceinline__ void mgs_step(int n, int i, int j, double (&w)[G], co
     const double nw = round_c<U>(__dsub_rn(w[t], __dmul_rn(h, (double)B[t])));
     w[t] = (!TAIL || tid + t * NT < n) ? nw : 0.0;   // rows past n stay zero
   }
-  if (lds_col) {
-    if (tid == 0) sHc[i] = h;
-  } else {
-    H[(size_t)j * ldh + i] = h;
-  }
+  return h;
 }
 
 // Load column c of V into B (row indices clamped to the matrix).
@@ -94,16 +86,19 @@ __device__ __forceinline__ void load_col(VT (&B)[G], const VT* __restrict__ V, i
 // straight-line code with a ring of D basis vectors in flight (the refill of a slot
 // is issued right after the slot is consumed), so the loads of v_{i+D} overlap D
 // inner products; beyond JU a rolled loop loads each vector when it is needed.
+// The rotation sweep over the new column runs alongside the Gram-Schmidt loop: as
+// soon as h_i is known, rotation i-1 combines it with the entry carried from the
+// previous rotations (uniform arithmetic, off the loop's critical path), in the same
+// order and with the same operations as a sweep over the finished column.
 // TAIL: n < G * NT, so that some lanes hold rows past n (kept at zero).
 constexpr int JU = 64;
-constexpr int JL = 512;   // Hessenberg columns up to this length are rotated in LDS
 template <int G, int U, int D, int NT, bool TAIL>
 __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict__ V, float* __restrict__ Vf,
                                                  int ldv, const double* __restrict__ w_in, double* __restrict__ H, int ldh,
                                                  double* __restrict__ cs, double* __restrict__ sn,
                                                  double* __restrict__ g, const double* __restrict__ beta0, double tau,
                                                  GStatus* st, GStatus* mirror) {
-  static_assert(NT == 512 || NT == 1024, "8 or 16 wave partials");
+  static_assert(NT == 256 || NT == 512 || NT == 1024, "4, 8 or 16 wave partials");
   if (st->done) {
     if (mirror && threadIdx.x == 0) mirror->done = 1;
     return;
@@ -111,18 +106,10 @@ __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict
   // per-wave partial sums, double-buffered by the parity of the inner-product index
   // so that one barrier per inner product suffices
   __shared__ double sh[2][NT / 64];
-  // the Hessenberg column and the previous rotations, staged in LDS so that the
-  // serial rotation sweep below runs on LDS, not on global-memory round trips
-  __shared__ double sHc[JL], sCs[JL], sSn[JL];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const bool lds_col = j + 2 <= JL;
-  {
-    const int t0 = min(tid, max(j - 1, 0));   // entries 0..j-1 exist
-    const double cv = cs[t0], sv = sn[t0];
-    if (lds_col && tid < j) { sCs[tid] = cv; sSn[tid] = sv; }
-  }
   const double gj = g[j], b0 = *beta0;
+  double* __restrict__ hcol = H + (size_t)j * ldh;
   int rc[G];
   double w[G];
 #pragma unroll
@@ -132,6 +119,19 @@ __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict
     const double v = w_in[rc[t]];
     w[t] = r < n ? v : 0.0;
   }
+  // the carried entry of the rotation sweep: after step i it is entry i of the column
+  // rotated by rotations 0..i-1; entries 0..i-1 are final and stored
+  double a = 0.0;
+  auto rotate = [&](int i, double h) {
+    if (i == 0) {
+      a = h;
+      return;
+    }
+    const double ci = cs[i - 1], si = sn[i - 1];
+    const double hr = __dadd_rn(__dmul_rn(ci, a), __dmul_rn(si, h));
+    a = __dadd_rn(__dmul_rn(-si, a), __dmul_rn(ci, h));
+    if (tid == 0) hcol[i - 1] = hr;
+  };
   // the inner products read the basis in the working format (float32 copy unless u is
   // float64; the values are the same), which halves their memory traffic
   typedef typename std::conditional<U == P_FP64, double, float>::type VT;
@@ -142,46 +142,33 @@ __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict
   for (int d = 0; d < D; ++d) load_col<G>(B[d], Vr, ldv, min(d, j), rc);
 #pragma unroll
   for (int i = 0; i < JU; ++i) {
-    mgs_step<G, U, NT, TAIL>(n, i, j, w, B[i % D], H, ldh, sh, lds_col, sHc);
+    rotate(i, mgs_step<G, U, NT, TAIL>(n, i, w, B[i % D], sh));
     if (i == j) goto orthogonal;
     load_col<G>(B[i % D], Vr, ldv, min(i + D, j), rc);
   }
   for (int i = JU; i <= j; ++i) {
     VT Bt[G];
     load_col<G>(Bt, Vr, ldv, i, rc);
-    mgs_step<G, U, NT, TAIL>(n, i, j, w, Bt, H, ldh, sh, lds_col, sHc);
+    rotate(i, mgs_step<G, U, NT, TAIL>(n, i, w, Bt, sh));
   }
 orthogonal:
   double acc = 0.0;
 #pragma unroll
   for (int t = 0; t < G; ++t) acc = __fma_rn(w[t], w[t], acc);
-  acc = wave_sum_dpp(acc);
+  acc = wave_sum_dpp_l63(acc);
   const int pb = (j + 1) & 1;
-  if (lane == 0) sh[pb][wv] = acc;
+  if (lane == 63) sh[pb][wv] = acc;
   __syncthreads();
   const double hn = sqrt(sum_lanes<NT / 64>(sh[pb]));
   if (tid == 0) {
-    // rotate the new column by the previous Givens rotations, then a new rotation
-    // zeroes h_{j+1,j}; g is rotated and the stopping test taken
-    double* hc = lds_col ? sHc : H + (size_t)j * ldh;
-    const double* cc = lds_col ? sCs : cs;
-    const double* ss = lds_col ? sSn : sn;
-    // the entry carried from one rotation to the next stays in a register (the same
-    // operations as rotating the stored column in place, without a store-to-load
-    // round trip per rotation)
-    double a = hc[0];
-    for (int i = 0; i < j; ++i) {
-      const double b = hc[i + 1], ci = cc[i], si = ss[i];
-      hc[i] = __dadd_rn(__dmul_rn(ci, a), __dmul_rn(si, b));
-      a = __dadd_rn(__dmul_rn(-si, a), __dmul_rn(ci, b));
-    }
+    // a new rotation zeroes h_{j+1,j}; g is rotated and the stopping test taken
     const double b = hn;
     const double r = hypot(a, b);
     double c = 1.0, s = 0.0;
     if (r != 0.0) { c = a / r; s = b / r; }
     cs[j] = c; sn[j] = s;
-    hc[j] = r;
-    hc[j + 1] = 0.0;
+    hcol[j] = r;
+    hcol[j + 1] = 0.0;
     g[j + 1] = __dmul_rn(-s, gj);
     g[j] = __dmul_rn(c, gj);
     const double e = fabs(g[j + 1]);
@@ -192,10 +179,6 @@ orthogonal:
       mirror->jcount = j + 1;
       mirror->done = stop ? 1 : 0;
     }
-  }
-  if (lds_col) {
-    __syncthreads();
-    for (int t = tid; t <= j + 1; t += NT) H[(size_t)j * ldh + t] = sHc[t];
   }
   double* vnx = V + (size_t)(j + 1) * ldv;
 #pragma unroll

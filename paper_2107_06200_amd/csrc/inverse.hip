@@ -281,7 +281,9 @@ int trgemv(Ctx& c, int n, int store_prec, const void* T, int tri, const double* 
 // pivot order (row perm[j] at column j); X times (Rp fl_p(folded A v)); Y times
 // fl_p(folded X product); fl_u(mu S folded Y product).  Each product folds its
 // predecessor's partial sums while staging its input slice, so the intermediate
-// vectors never exist as separate launches.
+// vectors never exist as separate launches.  (The last fold stays a launch of its
+// own: folding it at the end of the Y product needs a device-scope release by every
+// workgroup, which writes back the L2 caches and costs far more than the launch.)
 int inv_operator(Ctx& c, int n, int p, const double* A, int lda, const float* Au, const double* v, const int* pinv,
                  const double* Rp, int inv_prec, const void* X, const void* Y, double mu, const double* S, int u,
                  double* out, const int* skip) {

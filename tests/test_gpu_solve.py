@@ -362,15 +362,21 @@ def test_multi_rhs_shared_factors_vs_oracle(M, h, cfg, n, nrhs, lu_update):
 
 
 def test_batched_matches_single(M, h):
+    # the persistent batched path (its own blocked LU and substitution) and the
+    # single-system path both reach the backward-error target; with kappa = 1e2 their
+    # solutions then agree to within kappa * n * 1e-15 relative
     sys_ = [WL.randsvd(n, 1e2, 2, WL.rng_for(27, n)) for n in (40, 90, 130)]
     As = [torch.from_numpy(np.asfortranarray(a)).to(DEV) for a, _, _ in sys_]
     bs = [torch.from_numpy(b).to(DEV) for _, _, b in sys_]
-    xs, outs, rc = M.solve_batched(h, As, bs)
+    xs, outs, _, rc = M.solve_batched(h, As, bs)
     assert rc == 0
     for (a, x, b), xg, o in zip(sys_, xs, outs):
         assert o.nbe <= 1e-15
-        xi, _, _, _ = M.solve(h, M.colmajor(torch.from_numpy(np.asfortranarray(a)).to(DEV)), torch.from_numpy(b).to(DEV))
-        assert torch.equal(xi, xg)
+        xi, oi, _, _ = M.solve(h, M.colmajor(torch.from_numpy(np.asfortranarray(a)).to(DEV)), torch.from_numpy(b).to(DEV))
+        assert oi.nbe <= 1e-15
+        n = a.shape[0]
+        rel = float((xi - xg).abs().max() / xi.abs().max())
+        assert rel <= 1e2 * n * 1e-15, rel
 
 
 @pytest.mark.parametrize("rho", [0.5, 0.9])
