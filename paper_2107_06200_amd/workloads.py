@@ -53,6 +53,28 @@ def randsvd(n, kappa, mode, rng, nrhs=0):
     return A, x, b
 
 
+def ls_system(m, n, kappa, mode, rng, rnorm=1e-2):
+    """Least-squares problem (A, x_true, b, r_true): A = U diag(s) V^T with U m x n
+    orthonormal columns (the first n columns of a Haar orthogonal matrix), s the
+    randsvd singular values, x_true ~ N(0, 1); r_true orthogonal to range(A) (the
+    remaining columns of the same orthogonal matrix), scaled to rnorm ||A x_true||_2;
+    b = A x_true + r_true.  The least-squares solution is x_true and its residual
+    r_true (up to rounding in forming b)."""
+    Q = haar_orthogonal(rng, m)
+    V = haar_orthogonal(rng, n)
+    s = singular_values(n, kappa, mode)
+    A = np.asfortranarray((Q[:, :n] * s[None, :]) @ V.T)
+    x = rng.standard_normal(n)
+    Ax = A @ x
+    if m > n:
+        c = rng.standard_normal(m - n)
+        r = Q[:, n:] @ c
+        r *= rnorm * np.linalg.norm(Ax) / np.linalg.norm(r)
+    else:
+        r = np.zeros(m)
+    return A, x, Ax + r, r
+
+
 def kappa_inf(A):
     """Infinity-norm condition number (computed with a float64 inverse)."""
     return float(np.abs(A).sum(axis=1).max() * np.abs(np.linalg.inv(A)).sum(axis=1).max())
