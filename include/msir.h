@@ -191,6 +191,27 @@ MSIR_API int msir_solve_csr(msir_handle* h, int n, int nnz, const int* drowptr, 
                    const double* dvals, const double* db, double* dx, const double* dx_true,
                    const msir_params* params, msir_result* out, msir_step* hist, int hist_cap, int* hist_len);
 
+/* Least squares: min ||b - A x||_2, the extension of the multistage approach to
+ * least squares problems that Sec. 4 names as future work.  Alg. 4 runs unchanged
+ * on the augmented system [[alpha I, A], [A^T, 0]] [y; x] = [b; 0] of order
+ * N = m + n, whose second block row is the normal equations A^T r = 0 for the
+ * residual r = b - A x = alpha y.  dA: m x n float64 column-major (lda >= m),
+ * m >= n, full column rank; db: m; dx: n (output); dr: NULL or m (output, the
+ * residual alpha y).  alpha: 0 for the default (the largest power of two not above
+ * max |a_ij|), else a positive power of two (alpha I and alpha y are then exact;
+ * the augmented matrix is best conditioned near sigma_min(A) / sqrt(2));
+ * *alpha_used (host, may be NULL) receives the value used.  The history, out
+ * (nbe, cbe, ferr, n_lu) and the convergence test refer to the augmented system;
+ * params as for msir_solve (CONV_TRUE is not available: -7).  The handle holds
+ * the augmented matrix (N^2 float64).  Errors: -1 h NULL, MSIR_ERR_SIZE m or n < 1
+ * or m + n > MSIR_MAX_N, -2 m < n, -3 dA NULL, -4 lda < m, -5 db NULL, -6 dx NULL,
+ * -8 bad params, -9 alpha negative, not finite or not a power of two,
+ * -11 hist_cap < 0; otherwise the return value of msir_solve on the augmented
+ * system.                                                                       */
+MSIR_API int msir_lstsq(msir_handle* h, int m, int n, const double* dA, int lda, const double* db, double alpha,
+               double* dx, double* dr, double* alpha_used, const msir_params* params, msir_result* out,
+               msir_step* hist, int hist_cap, int* hist_len);
+
 /* GMRES-IR5: the five-precision GMRES-based refinement of Sec. 1 (u_f, u, u_r,
  * u_g, u_p), without the multistage controller.  One LU in params->uf (scaling
  * policy params->scaling), x0 from the factors, then steps: r = b - A x in

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmsir.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["blas.hip", "gemv.hip", "getrf.hip", "trsv.hip", "gmres.hip", "util.hip", "inverse.hip", "sparse.hip", "noalloc.hip", "batched.hip", "msir.cpp", "server.cpp"]
+SOURCES = ["blas.hip", "gemv.hip", "getrf.hip", "trsv.hip", "gmres.hip", "util.hip", "inverse.hip", "sparse.hip", "noalloc.hip", "batched.hip", "lstsq.hip", "msir.cpp", "server.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950", "-ffp-contract=off",

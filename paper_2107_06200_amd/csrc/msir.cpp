@@ -280,6 +280,7 @@ struct msir_handle {
   int factorizations = 0;        // factorizations performed (counter for the results)
   bool au_valid = false;         // Au holds fl32(A) of the cached A (share mode)
   DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Acsr, Bws;
+  DevBuf Kls, fls, zls, cls;   // least squares: augmented matrix, its right-hand side and solution, column maxima
   int batch_grid_lu = 256, batch_grid_ref = 512;   // persistent workgroups of the batched launches
   double* dev_small = nullptr;   // device scalars
   double* host_small = nullptr;  // pinned host scalars
@@ -672,7 +673,7 @@ int msir_destroy(msir_handle* h) {
   Ctx& c = h->c;
   DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.part_x, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
                     &c.tmp_scalar, &c.moved, &c.tr_part, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
-                    &h->tmp2, &h->Acsr, &h->Bws};
+                    &h->tmp2, &h->Acsr, &h->Bws, &h->Kls, &h->fls, &h->zls, &h->cls};
   for (DevBuf* b : bufs) c.release(b->p, b->bytes);
   for (FactorSlot& s : h->slot) {
     DevBuf* ib[] = {&s.Xd, &s.Yd, &s.Xf, &s.Yf};
@@ -1646,6 +1647,45 @@ int msir_solve_csr(msir_handle* h, int n, int nnz, const int* drowptr, const int
   c.sp = &a;
   rc = msir_solve(h, n, Ad, n, db, dx, dxt, params, out, hist, hist_cap, hist_len);
   c.sp = nullptr;
+  return rc;
+}
+
+int msir_lstsq(msir_handle* h, int m, int n, const double* dA, int lda, const double* db, double alpha, double* dx,
+               double* dr, double* alpha_used, const msir_params* params, msir_result* out, msir_step* hist,
+               int hist_cap, int* hist_len) {
+  if (!h) return -1;
+  if (m < 1 || n < 1 || (long long)m + n > MSIR_MAX_N) return MSIR_ERR_SIZE;
+  if (m < n) return -2;
+  if (!dA) return -3;
+  if (lda < m) return -4;
+  if (!db) return -5;
+  if (!dx) return -6;
+  if (!(alpha >= 0.0) || !isfinite(alpha)) return -9;
+  if (alpha > 0.0) {
+    int e;
+    if (frexp(alpha, &e) != 0.5) return -9;   // not a power of two
+  }
+  const int N = m + n;
+  msir_params P;
+  if (params) P = *params; else msir_params_default(&P);
+  if (int e = check_params(N, P, false)) return e;
+  if (hist_cap < 0) return -11;
+  Ctx& c = h->c;
+  HIP_CHECK(hipSetDevice(c.device));
+  double* K = (double*)c.grow(h->Kls, (size_t)N * N * sizeof(double));
+  double* f = vbuf(h, h->fls, N);
+  double* z = vbuf(h, h->zls, N);
+  double* cm = vbuf(h, h->cls, (size_t)n + 1);   // column maxima, then alpha
+  if (!K || !f || !z || !cm) return MSIR_ERR_ALLOC;
+  int rc = lstsq_augment(c, m, n, dA, lda, db, alpha, cm, cm + n, K, f);
+  if (rc) return rc;
+  rc = msir_solve(h, N, K, N, f, z, nullptr, &P, out, hist, hist_cap, hist_len);
+  if (rc < 0) return rc;
+  if (int e = lstsq_split(c, m, n, z, cm + n, dx, dr)) return e;
+  if (alpha_used) {
+    if (int e = sync_read(h, cm + n, 1)) return e;
+    *alpha_used = h->host_small[0];
+  }
   return rc;
 }
 

@@ -193,6 +193,14 @@ struct GemvIn {
   const double* xscale = nullptr;
   const int* prow = nullptr;
 };
+// Least squares (lstsq.hip): the augmented matrix K = [[alpha I, A], [A^T, 0]] of order
+// m + n (ld m + n) and f = [b; 0]; alpha_dev[0] receives alpha (alpha_in > 0: that
+// value; else the largest power of two <= max |a_ij|).  colmax: n doubles of scratch.
+int lstsq_augment(Ctx& c, int m, int n, const double* A, int lda, const double* b, double alpha_in,
+                  double* colmax, double* alpha_dev, double* K, double* f);
+// x = z[m..m+n), r = alpha z[0..m) (r may be null)
+int lstsq_split(Ctx& c, int m, int n, const double* z, const double* alpha_dev, double* x, double* r);
+
 int gemv_partials(Ctx& c, const GemvPlan& g, int n, int a_prec, const void* A, int lda, const GemvIn& in, int mode,
                   double* ph, double* pl, double* px, const int* skip);
 // a_prec FP32 (mode 0 only) or FP64; mode 0 float64 sums into ph, 1 double-double into

@@ -65,7 +65,7 @@ class Completion(ctypes.Structure):
 
 
 SYMBOLS = ["msir_create", "msir_destroy", "msir_params_default", "msir_nb_auto", "msir_workspace_bytes",
-           "msir_status_string", "msir_solve", "msir_solve_csr", "msir_gmres_ir5", "msir_solve_multi", "msir_solve_batched", "msir_convert",
+           "msir_status_string", "msir_solve", "msir_solve_csr", "msir_gmres_ir5", "msir_lstsq", "msir_solve_multi", "msir_solve_batched", "msir_convert",
            "msir_scaling", "msir_getrf", "msir_getrs", "msir_round", "msir_residual", "msir_residual_noalloc", "msir_gmres", "msir_backward_error",
            "msir_timing", "msir_timing_get", "msir_server_create", "msir_server_submit", "msir_server_poll",
            "msir_server_destroy"]
@@ -90,6 +90,8 @@ _SIG = {
                             ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_gmres_ir5": (_I, [_P, _I, _P, _I, _P, _P, _P, ctypes.POINTER(Params), _I, _I, ctypes.POINTER(Result),
                             ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
+    "msir_lstsq": (_I, [_P, _I, _I, _P, _I, _P, _D, _P, _P, ctypes.POINTER(_D), ctypes.POINTER(Params),
+                        ctypes.POINTER(Result), ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_solve_multi": (_I, [_P, _I, _I, _P, _I, _P, _I, _P, _I, _P, _I, ctypes.POINTER(Params),
                               ctypes.POINTER(Result), ctypes.POINTER(Step), _I, ctypes.POINTER(_I)]),
     "msir_solve_batched": (_I, [_P, _I, ctypes.POINTER(_I), ctypes.POINTER(_P), ctypes.POINTER(_I),
@@ -269,6 +271,26 @@ def gmres_ir5(h, A, b, ug, up, x_true=None, P=None, hist_cap=4096, x=None):
                               H, hist_cap, ctypes.byref(hl))
     _check(rc, "msir_gmres_ir5")
     return x, res, [H[i] for i in range(min(hl.value, hist_cap))], rc
+
+
+def lstsq(h, A, b, alpha=0.0, P=None, hist_cap=4096, x=None, r=None):
+    """min ||b - A x||_2 by Alg. 4 on the augmented system (A m x n, m >= n).
+    Returns (x, r, alpha used, Result, [Step...], status)."""
+    A = colmajor(A)
+    m, n = A.shape
+    if x is None:
+        x = torch.empty(n, dtype=torch.float64, device=A.device)
+    if r is None:
+        r = torch.empty(m, dtype=torch.float64, device=A.device)
+    res = Result()
+    H = (Step * hist_cap)()
+    hl = ctypes.c_int(0)
+    au = ctypes.c_double(0.0)
+    rc = lib().msir_lstsq(h.h, m, n, _ptr(A), _ld(A), _ptr(b), float(alpha), _ptr(x), _ptr(r), ctypes.byref(au),
+                          ctypes.byref(P) if P is not None else None, ctypes.byref(res), H, hist_cap,
+                          ctypes.byref(hl))
+    _check(rc, "msir_lstsq")
+    return x, r, au.value, res, [H[i] for i in range(min(hl.value, hist_cap))], rc
 
 
 def solve_multi(h, A, B, X_true=None, P=None, hist_cap=512, X=None):
