@@ -171,3 +171,45 @@ def test_config3_full_size_default_operator(M, h, c3, uf):
     # forward error implied by the backward error (first-order perturbation bound)
     kinf = WL.kappa_inf(A)
     assert np.abs(xg - x).max() / np.abs(x).max() <= 4 * kinf * nbe_host + 1e-15
+
+
+def test_config2_operator_inverse_vs_substitution(M, h):
+    """The GMRES operator through explicit inverses, at the benchmark workload's full size.
+
+    The oracle factors the n = 4096 system (column scaling, fp16, DM(16)); the GPU applies
+    M^{-1} = mu S U^{-1} L^{-1} P R to a few vectors in precision p in both operator modes
+    (float64 inverses rounded to p, and substitution in p) and the oracle in float64
+    substitution.  Both GPU modes carry an error of the kind kappa(T) u_p; the inverse
+    mode must stay within a factor 50 of the substitution mode (its rounding is amplified
+    by kappa(L) and kappa(U) rather than by the componentwise condition of the solve).
+    The measured errors are printed (OPERR lines)."""
+    from oracle import fmt as F
+    from oracle import lu as OLU
+    from oracle import scaling as OSC
+    from oracle import solve as OSV
+    A, x, b = WL.config_system(2)
+    n = A.shape[0]
+    scal = OSC.compute(A, "fp16", rows=False)
+    Af = F.round_to(OSC.apply(A, *scal), "fp16")
+    W, piv, info = OLU.getrf(Af, "fp16", OLU.nb_auto(n, "fp16"))[:3]
+    assert info == 0
+    Wd = M.colmajor(torch.from_numpy(np.asfortranarray(W)).to(M.TORCH_DTYPE[M.PREC["fp16"]]).to(DEV))
+    ip = torch.from_numpy(piv.astype(np.int32)).to(DEV)
+    R = torch.from_numpy(np.ascontiguousarray(scal[0])).to(DEV)
+    S = torch.from_numpy(np.ascontiguousarray(scal[1])).to(DEV)
+    mu = scal[2]
+    rng = np.random.default_rng(11)
+    for comp in ("fp32", "fp64"):
+        worst = []
+        for k in range(3):
+            t = rng.standard_normal(n)
+            want = OSV.lu_solve(W, piv, t, "fp64", scal)
+            tt = torch.from_numpy(t).to(DEV)
+            inv = M.getrs(h, Wd, "fp16", ip, tt, comp, R, S, mu, mode=1).cpu().numpy()
+            sub = M.getrs(h, Wd, "fp16", ip, tt, comp, R, S, mu, mode=0).cpu().numpy()
+            e_inv = float(np.abs(inv - want).max() / np.abs(want).max())
+            e_sub = float(np.abs(sub - want).max() / np.abs(want).max())
+            print("OPERR n=%d p=%s vector %d: inverses %.3e substitution %.3e" % (n, comp, k, e_inv, e_sub))
+            worst.append((e_inv, e_sub))
+            assert np.all(np.isfinite(inv)) and np.all(np.isfinite(sub))
+            assert e_inv <= 50 * max(e_sub, 64 * F.u(comp)), (comp, e_inv, e_sub)
