@@ -30,7 +30,8 @@
 //  3. k_gemm (64 x 64 tiles of A22, 256 threads each): A22 -= L21 U12 with the
 //     panel's L21 and U12 staged in LDS.  For u_f in {fp16, bf16} either as an
 //     fp32 fused multiply-add chain in increasing k or on the matrix cores (MFMA
-//     32x32x8 f16/bf16 with fp32 accumulation); fp32 factors as an fp32 chain or
+//     32x32x16 f16/bf16 for panels of 16 columns or more, 32x32x8 for 8-column
+//     panels, fp32 accumulation); fp32 factors as an fp32 chain or
 //     MFMA 32x32x2 f32; fp64 as a float64 fused multiply-add chain.  The result is
 //     rounded to u_f.  Look-ahead (k_panel_gemm): the next panel, whose columns the
 //     previous update has finished, is factored by workgroup 0 of the launch that
@@ -514,6 +515,27 @@ typedef _Float16 half4_t __attribute__((ext_vector_type(4)));
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float16_t __attribute__((ext_vector_type(16)));
 
+typedef _Float16 half8_t __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// gfx950's K = 16 form: lane (l mod 32, l / 32) supplies row l mod 32 of A and column
+// l mod 32 of B at k = 8 (l / 32) .. 8 (l / 32) + 7; the accumulator layout is that
+// of the K = 8 form.
+template <int P>
+__device__ __forceinline__ float16_t mfma_32x32x16(const uint16_t* a8, const uint16_t* b8, float16_t c) {
+  if constexpr (P == P_FP16) {
+    half8_t av, bv;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { av[i] = __builtin_bit_cast(_Float16, a8[i]); bv[i] = __builtin_bit_cast(_Float16, b8[i]); }
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(av, bv, c, 0, 0, 0);
+  } else {
+    bf16x8_t av, bv;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) { av[i] = __builtin_bit_cast(__bf16, a8[i]); bv[i] = __builtin_bit_cast(__bf16, b8[i]); }
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, bv, c, 0, 0, 0);
+  }
+}
+
 template <int P>
 __device__ __forceinline__ float16_t mfma_32x32x8(const uint16_t* a4, const uint16_t* b4, float16_t c) {
   if constexpr (P == P_FP16) {
@@ -594,16 +616,32 @@ __device__ __forceinline__ void gemm_tile(typename Store<P>::T* __restrict__ W, 
       }
     }
     stage_st();
+    if constexpr (KMAX % 16 == 0) {
+      // panels of 16 columns or more: K = 16 per instruction (k >= jb are zeros in LDS)
 #pragma unroll
-    for (int kk = 0; kk < KMAX; kk += 8) {
-      if (kk < jb) {
-        uint16_t a4[4], b4[4];
+      for (int kk = 0; kk < KMAX; kk += 16) {
+        if (kk < jb) {
+          uint16_t a8[8], b8[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          a4[e] = sA[tr + lc][kk + 4 * hi + e] ^ (uint16_t)0x8000;   // -L21 (exact)
-          b4[e] = sB[tc + lc][kk + 4 * hi + e];
+          for (int e = 0; e < 8; ++e) {
+            a8[e] = sA[tr + lc][kk + 8 * hi + e] ^ (uint16_t)0x8000;   // -L21 (exact)
+            b8[e] = sB[tc + lc][kk + 8 * hi + e];
+          }
+          acc = mfma_32x32x16<P>(a8, b8, acc);
         }
-        acc = mfma_32x32x8<P>(a4, b4, acc);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < KMAX; kk += 8) {
+        if (kk < jb) {
+          uint16_t a4[4], b4[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            a4[e] = sA[tr + lc][kk + 4 * hi + e] ^ (uint16_t)0x8000;   // -L21 (exact)
+            b4[e] = sB[tc + lc][kk + 4 * hi + e];
+          }
+          acc = mfma_32x32x8<P>(a4, b4, acc);
+        }
       }
     }
     if (vec) {
