@@ -28,7 +28,7 @@ constexpr int BR = kBatchMaxN / BT;     // rows per thread
 constexpr int BKMAX = 256;              // GMRES iterations per call at most
 constexpr int BCH = 16;                 // factor columns loaded per batch (diagonal blocks)
 constexpr int BCR = 8;                  // factor columns per batch for the rows off the block
-constexpr int BJ = 4;                   // matrix columns per batch in the products
+constexpr int BJ = 16;                  // matrix columns per batch in the products (loads in flight)
 
 // vectors of a system (offsets in units of n doubles)
 enum BVec { V_XA = 0, V_XB = 1, V_X0 = 2, V_RHAT = 3, V_D = 4, V_T = 5, V_TLO = 6, V_Y = 7, V_YLO = 8,
@@ -126,13 +126,23 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
     if (wv == 0) {
       const int r = b0 + lane;
       double ah = r < n ? L.acc[r] : 0.0, al = (dd && r < n) ? L.alo[r] : 0.0;
-      for (int k0 = 0; k0 < 64 && b0 + k0 < b1; k0 += BCH) {
-        LT lrc[BCH];
+      // the next batch of this row's factor entries is loaded while the current one is
+      // consumed (register double buffer; the column order is unchanged)
+      LT lnx[BCH];
+      auto load_l = [&](LT (&dst)[BCH], int k0) {
 #pragma unroll
         for (int u = 0; u < BCH; ++u) {
           const int c = b0 + k0 + u;
-          lrc[u] = (r < n && c < r) ? (LT)Store<P>::to_d(W[(size_t)c * n + r]) : LT(0);
+          const LT v = (LT)Store<P>::to_d(W[(size_t)min(c, n - 1) * n + min(r, n - 1)]);
+          dst[u] = (r < n && c < r) ? v : LT(0);
         }
+      };
+      load_l(lnx, 0);
+      for (int k0 = 0; k0 < 64 && b0 + k0 < b1; k0 += BCH) {
+        LT lrc[BCH];
+#pragma unroll
+        for (int u = 0; u < BCH; ++u) lrc[u] = lnx[u];
+        if (k0 + BCH < 64 && b0 + k0 + BCH < b1) load_l(lnx, k0 + BCH);
 #pragma unroll
         for (int u = 0; u < BCH; ++u) {
           const int k = k0 + u, c = b0 + k;
@@ -169,8 +179,9 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
       }
       const int nq = r0 < n ? (n - r0 + BT - 1) / BT : 0;
       if (nq > 0) {
-        for (int k0 = 0; k0 < 64 && b0 + k0 < b1; k0 += BCR) {
-          ST lv[BCR][BR];
+        // two register batches: the loads of batch k0 + BCR are in flight while batch
+        // k0 is consumed (columns still in increasing order)
+        auto load = [&](ST (&lv)[BCR][BR], int k0) {
 #pragma unroll
           for (int u = 0; u < BCR; ++u) {
             const size_t col = (size_t)min(b0 + k0 + u, n - 1) * n;
@@ -178,6 +189,8 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
             for (int q = 0; q < BR; ++q)
               if (q < nq) lv[u][q] = W[col + min(r0 + BT * q, n - 1)];
           }
+        };
+        auto use = [&](const ST (&lv)[BCR][BR], int k0) {
 #pragma unroll
           for (int u = 0; u < BCR; ++u) {
             const int c = b0 + k0 + u;
@@ -197,6 +210,19 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
                 }
             }
           }
+        };
+        ST la[BCR][BR], lb[BCR][BR];
+        const int kend = min(64, b1 - b0);   // columns of this block
+        load(la, 0);
+        for (int k0 = 0;;) {
+          if (k0 + BCR < kend) load(lb, k0 + BCR);
+          use(la, k0);
+          k0 += BCR;
+          if (k0 >= kend) break;
+          if (k0 + BCR < kend) load(la, k0 + BCR);
+          use(lb, k0);
+          k0 += BCR;
+          if (k0 >= kend) break;
         }
 #pragma unroll
         for (int q = 0; q < BR; ++q) {
@@ -216,14 +242,23 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
       double ah = r < n ? L.acc[r] : 0.0, al = (dd && r < n) ? L.alo[r] : 0.0;
       const double rin = r < n ? F.rinv[r] : 1.0;
       const double udiag = r < n ? Store<P>::to_d(W[(size_t)r * n + r]) : 1.0;
-      for (int k0 = 64 - BCH; k0 >= 0; k0 -= BCH) {
-        if (b0 + k0 >= b1) continue;
-        LT urc[BCH];
+      LT unx[BCH];
+      auto load_u = [&](LT (&dst)[BCH], int k0) {
 #pragma unroll
         for (int u = 0; u < BCH; ++u) {
           const int c = b0 + k0 + u;
-          urc[u] = (r < n && c < n) ? (LT)Store<P>::to_d(W[(size_t)c * n + r]) : LT(0);
+          const LT v = (LT)Store<P>::to_d(W[(size_t)min(c, n - 1) * n + min(r, n - 1)]);
+          dst[u] = (r < n && c < n) ? v : LT(0);
         }
+      };
+      int kt = 64 - BCH;
+      while (kt > 0 && b0 + kt >= b1) kt -= BCH;   // highest batch holding a column of the block
+      load_u(unx, kt);
+      for (int k0 = kt; k0 >= 0; k0 -= BCH) {
+        LT urc[BCH];
+#pragma unroll
+        for (int u = 0; u < BCH; ++u) urc[u] = unx[u];
+        if (k0 - BCH >= 0) load_u(unx, k0 - BCH);
 #pragma unroll
         for (int u = BCH - 1; u >= 0; --u) {
           const int k = k0 + u, c = b0 + k;
@@ -265,9 +300,8 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
       }
       const int nq = tid < b0 ? (b0 - tid + BT - 1) / BT : 0;
       if (nq > 0) {
-        for (int k0 = 64 - BCR; k0 >= 0; k0 -= BCR) {
-          if (b0 + k0 >= b1) continue;
-          ST uv[BCR][BR];
+        // as in the forward sweep, two register batches (columns in decreasing order)
+        auto load = [&](ST (&uv)[BCR][BR], int k0) {
 #pragma unroll
           for (int u = 0; u < BCR; ++u) {
             const size_t col = (size_t)min(b0 + k0 + u, n - 1) * n;
@@ -275,6 +309,8 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
             for (int q = 0; q < BR; ++q)
               if (q < nq) uv[u][q] = W[col + min(tid + BT * q, b0 - 1)];
           }
+        };
+        auto use = [&](const ST (&uv)[BCR][BR], int k0) {
 #pragma unroll
           for (int u = BCR - 1; u >= 0; --u) {
             const int c = b0 + k0 + u;
@@ -294,6 +330,21 @@ __device__ void b_solve(const BatchFactor& F, int n, int comp, const double* t_h
                 }
             }
           }
+        };
+        // the highest batch holding a column of the block, then downwards
+        int k0 = 64 - BCR;
+        while (k0 > 0 && b0 + k0 >= b1) k0 -= BCR;
+        ST ua[BCR][BR], ub[BCR][BR];
+        load(ua, k0);
+        for (;;) {
+          if (k0 - BCR >= 0) load(ub, k0 - BCR);
+          use(ua, k0);
+          k0 -= BCR;
+          if (k0 < 0) break;
+          if (k0 - BCR >= 0) load(ua, k0 - BCR);
+          use(ub, k0);
+          k0 -= BCR;
+          if (k0 < 0) break;
         }
 #pragma unroll
         for (int q = 0; q < BR; ++q) {
@@ -930,7 +981,7 @@ __device__ void b_run(BatchSys& S, const BParams& P, BLds& L) {
   __syncthreads();
 }
 
-__global__ __launch_bounds__(BT, 2) void k_brefine(BatchSys* __restrict__ sys, const int* __restrict__ list, int count,
+__global__ __launch_bounds__(BT, 1) void k_brefine(BatchSys* __restrict__ sys, const int* __restrict__ list, int count,
                                                 int* __restrict__ queue, BParams P) {
   __shared__ BLds L;
   __shared__ int s_q;

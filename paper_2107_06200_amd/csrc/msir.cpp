@@ -281,7 +281,7 @@ struct msir_handle {
   bool au_valid = false;         // Au holds fl32(A) of the cached A (share mode)
   DevBuf Au, x0, xa, xb, rhat, d, tmp_hi, tmp_lo, tmp2, Acsr, Bws;
   DevBuf Kls, fls, zls, cls;   // least squares: augmented matrix, its right-hand side and solution, column maxima
-  int batch_grid_lu = 256, batch_grid_ref = 512;   // persistent workgroups of the batched launches
+  int batch_grid_lu = 256, batch_grid_ref = 256;   // persistent workgroups of the batched launches
   double* dev_small = nullptr;   // device scalars
   double* host_small = nullptr;  // pinned host scalars
   std::vector<int> hpiv, hperm, hpinv;
