@@ -262,6 +262,7 @@ struct FactorSlot {
   FactorState f;
   DevBuf Xd, Yd, Xf, Yf;
   bool inv64 = false, inv32 = false;  // inverses of this factorization are valid
+  bool inv_pending = false, inv32_pending = false;   // being computed on the side stream
   bool valid = false;                 // f holds the factorization of the cached A
 };
 
@@ -286,9 +287,27 @@ struct msir_handle {
   double* host_small = nullptr;  // pinned host scalars
   std::vector<int> hpiv, hperm, hpinv;
   hipEvent_t ev[4];
+  // explicit inverses computed ahead of the GMRES stage, beside the SIR steps that read
+  // the same factors: the side stream and the event behind its last launch
+  hipStream_t side = nullptr;
+  hipEvent_t ev_side = nullptr, ev_main = nullptr;
+  bool side_busy = false;
 };
 
+// Waits (host) for the side stream and turns its pending inverses into valid ones.
+// Called before anything that may overwrite or free factors or inverses.
+static void side_drain(msir_handle* h) {
+  if (!h->side_busy) return;
+  (void)hipEventSynchronize(h->ev_side);
+  for (FactorSlot& s : h->slot) {
+    if (s.inv_pending) { s.inv64 = true; s.inv_pending = false; }
+    if (s.inv32_pending) { s.inv32 = true; s.inv32_pending = false; }
+  }
+  h->side_busy = false;
+}
+
 static void invalidate_factors(msir_handle* h) {
+  side_drain(h);
   for (FactorSlot& s : h->slot) s.valid = s.inv64 = s.inv32 = false;
   h->au_valid = false;
 }
@@ -335,6 +354,7 @@ static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, 
                      int update) {
   h->cur = &h->slot[h->share ? prec : 0];
   if (h->share && h->cur->valid && h->cur->f.prec == prec && h->cur->f.n == n) return 0;
+  side_drain(h);   // no side-stream launch may still read the factors about to be replaced
   h->cur->valid = false;
   int rc = ensure_factor(h, n, prec);
   if (rc) return rc;
@@ -405,10 +425,62 @@ static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, 
   return 0;
 }
 
+// Starts the float64 inverses of the current factors (and their fp32 copies when u is
+// fp32) on the side stream, behind everything already queued on the handle's stream.
+// The factors are only read from here on until the next factorization, which waits for
+// this work first (side_drain).  Any failure leaves the inverses to be computed on
+// demand by ensure_inverses.
+static void prefetch_inverses(msir_handle* h, int n, int u) {
+  FactorSlot& s = *h->cur;
+  if (s.inv64 || s.inv_pending) return;
+  Ctx& c = h->c;
+  if (!h->side) {
+    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { h->side = nullptr; return; }
+    if (hipEventCreateWithFlags(&h->ev_side, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      return;
+    }
+  }
+  double* Xd = (double*)c.grow(s.Xd, (size_t)n * n * sizeof(double));
+  double* Yd = (double*)c.grow(s.Yd, (size_t)n * n * sizeof(double));
+  float* Xf = nullptr;
+  float* Yf = nullptr;
+  if (u == P_FP32) {
+    Xf = (float*)c.grow(s.Xf, (size_t)n * n * sizeof(float));
+    Yf = (float*)c.grow(s.Yf, (size_t)n * n * sizeof(float));
+  }
+  if (!Xd || !Yd || (u == P_FP32 && (!Xf || !Yf))) return;
+  if (hipEventRecord(h->ev_main, c.stream) != hipSuccess || hipStreamWaitEvent(h->side, h->ev_main, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  hipStream_t main = c.stream;
+  c.stream = h->side;
+  int rc = tri_inverses(c, n, s.f.prec, s.f.W, n, Xd, Yd);
+  if (!rc && u == P_FP32) rc = square_to_f32(c, n, Xd, Xf);
+  if (!rc && u == P_FP32) rc = square_to_f32(c, n, Yd, Yf);
+  c.stream = main;
+  if (rc || hipEventRecord(h->ev_side, h->side) != hipSuccess) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipGetLastError();
+    return;
+  }
+  s.inv_pending = true;
+  s.inv32_pending = u == P_FP32;
+  h->side_busy = true;
+}
+
 // Inverses of the current factors in the operator precision p (FP32 or FP64).
 static int ensure_inverses(msir_handle* h, int n, int p, const void** X, const void** Y) {
   Ctx& c = h->c;
   FactorSlot& s = *h->cur;
+  if (s.inv_pending || s.inv32_pending) {
+    // computed ahead on the side stream: the handle's stream waits for them
+    HIP_CHECK(hipStreamWaitEvent(c.stream, h->ev_side, 0));
+    if (s.inv_pending) { s.inv64 = true; s.inv_pending = false; }
+    if (s.inv32_pending) { s.inv32 = true; s.inv32_pending = false; }
+  }
   if (!s.inv64) {
     double* Xd = (double*)c.grow(s.Xd, (size_t)n * n * sizeof(double));
     double* Yd = (double*)c.grow(s.Yd, (size_t)n * n * sizeof(double));
@@ -670,6 +742,8 @@ int msir_destroy(msir_handle* h) {
   if (!h) return 0;
   (void)hipSetDevice(h->c.device);
   (void)hipStreamSynchronize(h->c.stream);
+  side_drain(h);
+  if (h->side) (void)hipStreamSynchronize(h->side);
   Ctx& c = h->c;
   DevBuf* bufs[] = {&c.part_hi, &c.part_lo, &c.part_x, &c.r_hi, &c.r_lo, &c.mon_part, &c.flags, &c.yfwd, &c.xbwd,
                     &c.tmp_scalar, &c.moved, &c.tr_part, &h->Au, &h->x0, &h->xa, &h->xb, &h->rhat, &h->d, &h->tmp_hi, &h->tmp_lo,
@@ -689,6 +763,9 @@ int msir_destroy(msir_handle* h) {
     delete[] c.ev_cls;
   }
   c.release(c.counter, 0);
+  if (h->ev_side) (void)hipEventDestroy(h->ev_side);
+  if (h->ev_main) (void)hipEventDestroy(h->ev_main);
+  if (h->side) (void)hipStreamDestroy(h->side);
   if (h->host_small) (void)hipHostFree(h->host_small);
   for (int i = 0; i < 4; ++i) (void)hipEventDestroy(h->ev[i]);
   delete h;
@@ -1075,6 +1152,9 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
   const int fact0 = h->factorizations;
   rc = do_factor(h, n, dA, lda, uf, P.scaling, nb, P.lu_update);
   if (rc) return rc;
+  // the first level's GMRES operator (if SIR does not converge) uses the inverses of
+  // these factors: start them now, beside x0 and the SIR steps
+  if (P.gmres_op == MSIR_OP_INVERSE) prefetch_inverses(h, n, u);
   float* Au = nullptr;
   if (u == P_FP32) {
     Au = (float*)c.grow(h->Au, (size_t)n * n * sizeof(float));
@@ -1247,6 +1327,9 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
       if (!have_phi0) { phi0 = phi; have_phi0 = true; }
       dprev = delta;
       trigger = z <= uxr || v >= P.rho_thresh || it >= P.i_max || (alg != 0 && k >= k_max) || phi <= sqn * uxr;
+      // after an escalation: SIR contracting slowly is likely to hand over to GMRES, whose
+      // operator needs the new factors' inverses; start them beside the SIR steps
+      if (alg == 0 && level > 0 && v > 0.1 && P.gmres_op == MSIR_OP_INVERSE) prefetch_inverses(h, n, u);
       std::swap(x, xn);
       xnorm = mxn;
       cached = false;
