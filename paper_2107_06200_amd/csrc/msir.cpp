@@ -263,6 +263,9 @@ struct FactorSlot {
   DevBuf Xd, Yd, Xf, Yf;
   bool inv64 = false, inv32 = false;  // inverses of this factorization are valid
   bool inv_pending = false, inv32_pending = false;   // being computed on the side stream
+  bool spec_pending = false;          // factorization queued on the side stream ahead of an escalation
+  const double* spec_A = nullptr;     // ... of this matrix
+  int spec_lda = 0;
   bool valid = false;                 // f holds the factorization of the cached A
 };
 
@@ -308,7 +311,7 @@ static void side_drain(msir_handle* h) {
 
 static void invalidate_factors(msir_handle* h) {
   side_drain(h);
-  for (FactorSlot& s : h->slot) s.valid = s.inv64 = s.inv32 = false;
+  for (FactorSlot& s : h->slot) s.valid = s.inv64 = s.inv32 = s.spec_pending = false;
   h->au_valid = false;
 }
 
@@ -350,11 +353,21 @@ static int sync_read(msir_handle* h, const double* dev, int count) {
 
 // Factor A in u_f = prec with the Sec. 2.1.2 policy.  Leaves the factors in the slot
 // of that level (h->cur).  In share mode a valid slot is reused as it is.
+static int finish_factor(msir_handle* h, int n, int prec, const int* dinfo);
+static int* spec_info(const FactorState& f);
+
 static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, int scaling_mode, int nb,
                      int update) {
-  h->cur = &h->slot[h->share ? prec : 0];
+  h->cur = &h->slot[prec];
   if (h->share && h->cur->valid && h->cur->f.prec == prec && h->cur->f.n == n) return 0;
-  side_drain(h);   // no side-stream launch may still read the factors about to be replaced
+  side_drain(h);   // no side-stream launch may still read or write factors from here on
+  if (h->cur->spec_pending && h->cur->f.prec == prec && h->cur->f.n == n && h->cur->spec_A == A &&
+      h->cur->spec_lda == lda) {
+    // factored ahead on the side stream (same conversion and getrf): finish on the host
+    h->cur->spec_pending = false;
+    return finish_factor(h, n, prec, spec_info(h->cur->f));
+  }
+  h->cur->spec_pending = false;
   h->cur->valid = false;
   int rc = ensure_factor(h, n, prec);
   if (rc) return rc;
@@ -397,11 +410,23 @@ static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, 
     }
     break;
   }
-  // interchanges -> permutation (host), reciprocals of U's diagonal
+  return finish_factor(h, n, prec, (const int*)(h->dev_small + 16));
+}
+
+// Device int of a slot for the info of a factorization queued ahead (the last 64 bytes
+// of the slot's vector buffer are spare).
+static int* spec_info(const FactorState& f) { return (int*)((char*)f.rinv + f.vec_bytes - 64); }
+
+// After getrf on the handle's stream (or a side-stream factorization already waited
+// for): interchanges -> permutation (host), reciprocals of U's diagonal.
+static int finish_factor(msir_handle* h, int n, int prec, const int* dinfo) {
+  FactorState& f = h->cur->f;
+  Ctx& c = h->c;
+  int rc;
   h->hpiv.resize(n);
   h->hperm.resize(n);
   HIP_CHECK(hipMemcpyAsync(h->hpiv.data(), f.ipiv, n * sizeof(int), hipMemcpyDeviceToHost, c.stream));
-  HIP_CHECK(hipMemcpyAsync(h->host_small, h->dev_small + 16, sizeof(int), hipMemcpyDeviceToHost, c.stream));
+  HIP_CHECK(hipMemcpyAsync(h->host_small, dinfo, sizeof(int), hipMemcpyDeviceToHost, c.stream));
   HIP_CHECK(hipStreamSynchronize(c.stream));
   memcpy(&f.info, h->host_small, sizeof(int));
   for (int i = 0; i < n; ++i) h->hperm[i] = i;
@@ -425,6 +450,65 @@ static int do_factor(msir_handle* h, int n, const double* A, int lda, int prec, 
   return 0;
 }
 
+// The side stream (created on first use) and its events; false if they cannot be made.
+static bool ensure_side(msir_handle* h) {
+  if (h->side) return true;
+  if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+    h->side = nullptr;
+    (void)hipGetLastError();
+    return false;
+  }
+  if (hipEventCreateWithFlags(&h->ev_side, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return true;
+}
+
+// Queues the factorization in format prec (no scaling: the formats an escalation reaches)
+// on the side stream, into that format's slot, behind everything already queued on the
+// handle's stream.  The escalation that needs it waits for the side stream and finishes
+// it (do_factor); if none comes, it is discarded.  The computation is the one do_factor
+// performs (conversion, getrf with the same panel width and update), so the factors are
+// the same.  Any failure leaves the factorization to do_factor.
+static void speculate_factor(msir_handle* h, int n, const double* A, int lda, int prec, int nb, int update) {
+  if (prec == P_FP16 || prec == P_BF16 || prec < 0) return;
+  FactorSlot& s = h->slot[prec];
+  if ((s.valid && s.f.prec == prec && s.f.n == n) || s.spec_pending) return;
+  if (!ensure_side(h)) return;
+  side_drain(h);            // the slot may still be read by earlier side work
+  FactorSlot* saved = h->cur;
+  h->cur = &s;
+  s.valid = false;
+  int rc = ensure_factor(h, n, prec);
+  h->cur = saved;
+  if (rc) { (void)hipGetLastError(); return; }
+  s.inv64 = s.inv32 = false;
+  FactorState& f = s.f;
+  f.scaled = false;
+  f.mu = 1.0;
+  Ctx& c = h->c;
+  if (hipEventRecord(h->ev_main, c.stream) != hipSuccess || hipStreamWaitEvent(h->side, h->ev_main, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    return;
+  }
+  hipStream_t main = c.stream;
+  c.stream = h->side;
+  rc = convert(c, n, A, lda, prec, nullptr, nullptr, 1.0, f.W, n);
+  if (!rc) rc = getrf(c, n, prec, f.W, n, nb, f.ipiv, spec_info(f), update);
+  c.stream = main;
+  if (rc || hipEventRecord(h->ev_side, h->side) != hipSuccess) {
+    (void)hipStreamSynchronize(h->side);
+    (void)hipGetLastError();
+    return;
+  }
+  s.spec_pending = true;
+  s.spec_A = A;
+  s.spec_lda = lda;
+  h->side_busy = true;
+}
+
 // Starts the float64 inverses of the current factors (and their fp32 copies when u is
 // fp32) on the side stream, behind everything already queued on the handle's stream.
 // The factors are only read from here on until the next factorization, which waits for
@@ -434,14 +518,7 @@ static void prefetch_inverses(msir_handle* h, int n, int u) {
   FactorSlot& s = *h->cur;
   if (s.inv64 || s.inv_pending) return;
   Ctx& c = h->c;
-  if (!h->side) {
-    if (hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) { h->side = nullptr; return; }
-    if (hipEventCreateWithFlags(&h->ev_side, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&h->ev_main, hipEventDisableTiming) != hipSuccess) {
-      (void)hipGetLastError();
-      return;
-    }
-  }
+  if (!ensure_side(h)) return;
   double* Xd = (double*)c.grow(s.Xd, (size_t)n * n * sizeof(double));
   double* Yd = (double*)c.grow(s.Yd, (size_t)n * n * sizeof(double));
   float* Xf = nullptr;
@@ -1368,7 +1445,13 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
       }
       it = 0; dprev = INFINITY; rho_max = 0.0;
       if (alg == 0) { alg = 1; st.events |= MSIR_EV_SWITCH; }
-      else if (alg == 1) { alg = 2; st.events |= MSIR_EV_SWITCH; }
+      else if (alg == 1) {
+        alg = 2;
+        st.events |= MSIR_EV_SWITCH;
+        // GMRES-IR is the last variant before an escalation: queue the next format's
+        // factorization beside it (used only if the escalation comes)
+        speculate_factor(h, n, dA, lda, next_uf(uf), nb, P.lu_update);
+      }
       else {
         st.events |= MSIR_EV_ESCALATE;
         hist.push_back(st);
@@ -1690,6 +1773,7 @@ int msir_gmres_ir5(msir_handle* h, int n, const double* dA, int lda, const doubl
   if (up != MSIR_FP32 && up != MSIR_FP64 && up != MSIR_DD) return -9;
   if (hist_cap < 0) return -11;
   HIP_CHECK(hipSetDevice(h->c.device));
+  invalidate_factors(h);
   std::vector<msir_step> H;
   int rc = ir5_one(h, n, dA, lda, db, dx, dxt, P, ug, up, out, H);
   unsigned terr = 0;
