@@ -102,15 +102,20 @@ GEMV_SOURCES = ["paper_2107_06200_amd/csrc/gemv.hip", "paper_2107_06200_amd/csrc
 TRAFFIC_FILE = "profiles/msir_n4096_gemv_hbm_counters.md"
 
 
-def measured_traffic(cls, n):
+ARNOLDI_SOURCES = ["paper_2107_06200_amd/csrc/gmres.hip", "paper_2107_06200_amd/csrc/gmres.hpp",
+                   "paper_2107_06200_amd/csrc/common.hpp", "paper_2107_06200_amd/csrc/msir_internal.hpp"]
+ARNOLDI_TRAFFIC_FILE = "profiles/msir_n4096_arnoldi_hbm_counters.md"
+
+
+def measured_traffic(cls, n, path=TRAFFIC_FILE, sources=GEMV_SOURCES):
     """HBM bytes per launch of class `cls` from the committed counter summary (FETCH_SIZE and
     WRITE_SIZE runs calibrated on a copy of known size), or None when there is no figure for
     this class and order or the kernel sources have changed since the counters were taken."""
     import hashlib
     import re
     try:
-        txt = open(os.path.join(ROOT, TRAFFIC_FILE)).read()
-        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in GEMV_SOURCES)).hexdigest()[:16]
+        txt = open(os.path.join(ROOT, path)).read()
+        h = hashlib.sha256(b"".join(open(os.path.join(ROOT, p), "rb").read() for p in sources)).hexdigest()[:16]
     except OSError:
         return None
     if n != 4096:
@@ -519,7 +524,8 @@ def main():
         a_bytes = arnoldi_bytes(hist, n, prm["restart"], 4 if prm["u"] == "fp32" else 8)
         a_ach = a_bytes / (a_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": "arnoldi", "achieved": round(a_ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(a_ach / HBM_PEAK_GBS, 5), "traffic": None,
+                "unit": "GB/s", "frac": round(a_ach / HBM_PEAK_GBS, 5),
+                "traffic": measured_traffic("arnoldi", n, ARNOLDI_TRAFFIC_FILE, ARNOLDI_SOURCES),
                 "bytes_per_launch": round(a_bytes / max(1, a_launches)), "avg_launch_ms": round(a_ms / max(1, a_launches), 5),
                 "launches": a_launches,
                 "note": "latency-bound: one workgroup runs the j+1 dependent Gram-Schmidt reductions of a step"}

@@ -13,6 +13,8 @@
 // host only synchronises every few iterations.  After a cycle: y = R^{-1} g by one
 // wave, delta = fl_u(V y), d += delta; with a restart length the preconditioned
 // residual is updated as fl_u(c - fl_u(M^{-1} A delta)).
+#include <hip/hip_ext.h>
+
 #include "common.hpp"
 #include "msir_internal.hpp"
 #include "gmres.hpp"
@@ -192,43 +194,59 @@ orthogonal:
   }
 }
 
+// One launch; when the context's timing slot is open the slot's events travel in the
+// dispatch itself (start and end of the kernel, no separate event packets).
+template <int G, int U, int D, int NT, bool TAIL>
+static void launch_arnoldi_k(Ctx& c, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
+                             double* cs, double* sn, double* g, const double* beta0, double tau, GStatus* st,
+                             GStatus* mirror) {
+  if (c.ext_slot >= 0) {
+    const int sl = c.ext_slot;
+    c.ext_slot = -1;
+    hipExtLaunchKernelGGL(k_arnoldi<G, U, D, NT, TAIL>, dim3(1), dim3(NT), 0, c.stream, c.ev_pool[sl],
+                          c.ev_pool[sl + 1], 0, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
+  } else {
+    k_arnoldi<G, U, D, NT, TAIL><<<1, NT, 0, c.stream>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
+  }
+}
+
 template <int G, int D, int NT, bool TAIL>
-static void launch_arnoldi_t(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
+static void launch_arnoldi_t(Ctx& c, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
                              double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st,
                              GStatus* mirror) {
   switch (u) {
     case P_FP16:
-      k_arnoldi<G, P_FP16, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
+      launch_arnoldi_k<G, P_FP16, D, NT, TAIL>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
       break;
     case P_BF16:
-      k_arnoldi<G, P_BF16, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
+      launch_arnoldi_k<G, P_BF16, D, NT, TAIL>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
       break;
     case P_FP32:
-      k_arnoldi<G, P_FP32, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
+      launch_arnoldi_k<G, P_FP32, D, NT, TAIL>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
       break;
     default:
-      k_arnoldi<G, P_FP64, D, NT, TAIL><<<1, NT, 0, s>>>(n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
+      launch_arnoldi_k<G, P_FP64, D, NT, TAIL>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, st, mirror);
       break;
   }
 }
 
 template <int G, int D, int NT>
-static void launch_arnoldi_g(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
+static void launch_arnoldi_g(Ctx& c, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
                              double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st,
                              GStatus* mirror) {
-  if (n == G * NT) launch_arnoldi_t<G, D, NT, false>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
-  else launch_arnoldi_t<G, D, NT, true>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  if (n == G * NT) launch_arnoldi_t<G, D, NT, false>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else launch_arnoldi_t<G, D, NT, true>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
 }
 
 // values per thread G, basis vectors in flight D, threads NT (see above)
-static void launch_arnoldi(hipStream_t s, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
+static void launch_arnoldi(Ctx& c, int n, int j, double* V, float* Vf, int ldv, const double* w, double* H, int ldh,
                            double* cs, double* sn, double* g, const double* beta0, double tau, int u, GStatus* st,
-                             GStatus* mirror) {
-  if (n <= 512) launch_arnoldi_g<1, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
-  else if (n <= 1024) launch_arnoldi_g<2, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
-  else if (n <= 2048) launch_arnoldi_g<4, 8, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
-  else if (n <= 4096) launch_arnoldi_g<8, 4, 512>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
-  else launch_arnoldi_g<8, 2, 1024>(s, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+                           GStatus* mirror) {
+  if (n <= 512) launch_arnoldi_g<1, 8, 512>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else if (n <= 1024) launch_arnoldi_g<2, 8, 512>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else if (n <= 2048) launch_arnoldi_g<4, 8, 512>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else if (n <= 4096) launch_arnoldi_g<8, 4, 512>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else launch_arnoldi_g<8, 2, 1024>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
 }
 
 // y = R^{-1} g (upper triangular from the rotated Hessenberg), one wave,
@@ -325,8 +343,12 @@ int gmres(Ctx& c, GmresWork& gw, const GmresOp& op, const double* rhat, double t
       const bool check = it + 1 == next_check && it + 1 < m && wait_at < 0;
       if (it + 1 == next_check) next_check *= 2;
       if (check) *(volatile int*)&gw.host_mirror->done = 0;   // no launch writes it now
-      MSIR_TIMED(c, MSIR_T_ARNOLDI, launch_arnoldi(c.stream, n, it, gw.V, gw.Vf, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g,
-                                                   gw.beta0, tau, u, st, check ? gw.dev_mirror : nullptr));
+      {
+        const int tslot = c.tbegin_kernel(MSIR_T_ARNOLDI);
+        launch_arnoldi(c, n, it, gw.V, gw.Vf, ldv, gw.w, gw.H, ldh, gw.cs, gw.sn, gw.g, gw.beta0, tau, u, st,
+                       check ? gw.dev_mirror : nullptr);
+        c.tend_kernel(tslot);
+      }
       HIP_CHECK(hipGetLastError());
       if (check) {
         HIP_CHECK(hipEventRecord(gw.ev_mirror, c.stream));

@@ -494,10 +494,13 @@ static void speculate_factor(msir_handle* h, int n, const double* A, int lda, in
     return;
   }
   hipStream_t main = c.stream;
+  const bool timing = c.timing;   // the kernel-class timing covers the handle's stream only
   c.stream = h->side;
+  c.timing = false;
   rc = convert(c, n, A, lda, prec, nullptr, nullptr, 1.0, f.W, n);
   if (!rc) rc = getrf(c, n, prec, f.W, n, nb, f.ipiv, spec_info(f), update);
   c.stream = main;
+  c.timing = timing;
   if (rc || hipEventRecord(h->ev_side, h->side) != hipSuccess) {
     (void)hipStreamSynchronize(h->side);
     (void)hipGetLastError();
@@ -533,11 +536,14 @@ static void prefetch_inverses(msir_handle* h, int n, int u) {
     return;
   }
   hipStream_t main = c.stream;
+  const bool timing = c.timing;
   c.stream = h->side;
+  c.timing = false;
   int rc = tri_inverses(c, n, s.f.prec, s.f.W, n, Xd, Yd);
   if (!rc && u == P_FP32) rc = square_to_f32(c, n, Xd, Xf);
   if (!rc && u == P_FP32) rc = square_to_f32(c, n, Yd, Yf);
   c.stream = main;
+  c.timing = timing;
   if (rc || hipEventRecord(h->ev_side, h->side) != hipSuccess) {
     (void)hipStreamSynchronize(h->side);
     (void)hipGetLastError();
