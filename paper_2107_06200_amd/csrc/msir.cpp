@@ -450,6 +450,10 @@ static int finish_factor(msir_handle* h, int n, int prec, const int* dinfo) {
   return 0;
 }
 
+// Orders from which work is queued ahead on the side stream: below, the inverses and a
+// factorization take less time than the stream bookkeeping saves.
+constexpr int kSideMinN = 1024;
+
 // The side stream (created on first use) and its events; false if they cannot be made.
 static bool ensure_side(msir_handle* h) {
   if (h->side) return true;
@@ -1237,7 +1241,7 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
   if (rc) return rc;
   // the first level's GMRES operator (if SIR does not converge) uses the inverses of
   // these factors: start them now, beside x0 and the SIR steps
-  if (P.gmres_op == MSIR_OP_INVERSE) prefetch_inverses(h, n, u);
+  if (P.gmres_op == MSIR_OP_INVERSE && n >= kSideMinN) prefetch_inverses(h, n, u);
   float* Au = nullptr;
   if (u == P_FP32) {
     Au = (float*)c.grow(h->Au, (size_t)n * n * sizeof(float));
@@ -1412,7 +1416,8 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
       trigger = z <= uxr || v >= P.rho_thresh || it >= P.i_max || (alg != 0 && k >= k_max) || phi <= sqn * uxr;
       // after an escalation: SIR contracting slowly is likely to hand over to GMRES, whose
       // operator needs the new factors' inverses; start them beside the SIR steps
-      if (alg == 0 && level > 0 && v > 0.1 && P.gmres_op == MSIR_OP_INVERSE) prefetch_inverses(h, n, u);
+      if (alg == 0 && level > 0 && v > 0.1 && P.gmres_op == MSIR_OP_INVERSE && n >= kSideMinN)
+        prefetch_inverses(h, n, u);
       std::swap(x, xn);
       xnorm = mxn;
       cached = false;
@@ -1456,7 +1461,7 @@ static int solve_one(msir_handle* h, int n, const double* dA, int lda, const dou
         st.events |= MSIR_EV_SWITCH;
         // GMRES-IR is the last variant before an escalation: queue the next format's
         // factorization beside it (used only if the escalation comes)
-        speculate_factor(h, n, dA, lda, next_uf(uf), nb, P.lu_update);
+        if (n >= kSideMinN) speculate_factor(h, n, dA, lda, next_uf(uf), nb, P.lu_update);
       }
       else {
         st.events |= MSIR_EV_ESCALATE;
