@@ -147,7 +147,7 @@ typedef struct msir_handle msir_handle;
 #define MSIR_ERR_SIZE      -102   /* n outside [1, MSIR_MAX_N]                     */
 #define MSIR_ERR_TIMEOUT   -103   /* a substitution launch's bounded wait expired;
                                      its results are invalid                      */
-#define MSIR_MAX_N         8192   /* register-resident panel limit (see msir_nb_auto) */
+#define MSIR_MAX_N        16384   /* register-resident panel limit (see msir_nb_auto) */
 
 /* Create a handle on HIP device `device`.  `stream` is a hipStream_t (NULL: the
  * null stream).  `hbm_budget_bytes` caps the workspace the handle may allocate
@@ -160,7 +160,9 @@ MSIR_API int msir_destroy(msir_handle* h);
 MSIR_API void msir_params_default(msir_params* p);
 /* Panel width used for an n x n factorization whose arithmetic is fp32 (fmt in
  * {FP16, BF16, FP32}) or fp64 (FP64): the panel is held in registers of one
- * compute unit, 64 (fp32) or 32 (fp64) values per thread over 1024 threads.    */
+ * compute unit, 64 (fp32) or 32 (fp64) values per thread over 1024 threads:
+ * with R = ceil(n / 1024) rows per thread, nb = 64, 32, 16, 8, 4 for R <= 1, 2,
+ * 4, 8, 16, halved for fp64.                                                    */
 MSIR_API int msir_nb_auto(int n, msir_prec fmt);
 /* Bytes of device workspace msir_solve needs for order n under params.          */
 MSIR_API size_t msir_workspace_bytes(int n, const msir_params* p);

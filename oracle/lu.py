@@ -46,7 +46,7 @@ def nb_auto(n, fmt_f):
     compute unit (1024 threads, at most 64 fp32 or 32 fp64 values per thread), so the
     width is 64 / ceil(n / 1024) rounded down to a power of two, halved for fp64."""
     R = -(-n // 1024)
-    nb = 64 if R <= 1 else 32 if R <= 2 else 16 if R <= 4 else 8
+    nb = 64 if R <= 1 else 32 if R <= 2 else 16 if R <= 4 else 8 if R <= 8 else 4
     return nb // 2 if fmt_f == "fp64" else nb
 
 

@@ -757,6 +757,14 @@ __global__ __launch_bounds__(GNT) void k_gemm(typename Store<P>::T* __restrict__
 // previous launch updated) while the others apply the current block's trailing update
 // to tile columns 1, 2, ... (the columns right of the next panel's tile column), four
 // 64 x 64 tiles per workgroup of 1024 threads.  The two parts touch disjoint columns.
+// Depth of the update's tiles for panel width NB: at least one value per thread in a
+// tile load (4) and, for fp16 / bf16, one matrix-core step (8); depths beyond the
+// panel width are zero-filled.
+template <int P, int NB>
+constexpr int gemm_k() {
+  return (P == P_FP16 || P == P_BF16) ? (NB < 8 ? 8 : NB) : (NB < 4 ? 4 : NB);
+}
+
 template <int P, int R, int NB, bool MF>
 __global__ __launch_bounds__(PNT) void k_panel_gemm(typename Store<P>::T* __restrict__ W, int ldw, int n, int j0p,
                                                     int jbp, int* __restrict__ ipiv, int* __restrict__ info,
@@ -765,10 +773,11 @@ __global__ __launch_bounds__(PNT) void k_panel_gemm(typename Store<P>::T* __rest
     panel_body<P, R, NB>(W, ldw, n, j0p, jbp, ipiv, info, moved);
     return;
   }
-  __shared__ typename Store<P>::T sA[PNT / GNT][GT][NB + 4], sB[PNT / GNT][GT][NB + 4];
+  constexpr int GK = gemm_k<P, NB>();
+  __shared__ typename Store<P>::T sA[PNT / GNT][GT][GK + 4], sB[PNT / GNT][GT][GK + 4];
   const int sub = threadIdx.x / GNT;
   const int tile = (blockIdx.x - 1) * (PNT / GNT) + sub;
-  gemm_tile<P, NB, MF>(W, ldw, n, j0, jb, tile % mtiles, 1 + tile / mtiles, threadIdx.x % GNT, sA[sub], sB[sub]);
+  gemm_tile<P, GK, MF>(W, ldw, n, j0, jb, tile % mtiles, 1 + tile / mtiles, threadIdx.x % GNT, sA[sub], sB[sub]);
 }
 
 // ------------------------------------------------------------------ driver
@@ -785,7 +794,8 @@ static void panel_dispatch(Ctx& c, void* W, int ldw, int n, int j0, int jb, int*
   if (R <= 1) launch_panel<P, 1, NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
   else if (R <= 2 && 2 * NB <= CAP) launch_panel<P, (2 * NB <= CAP ? 2 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
   else if (R <= 4 && 4 * NB <= CAP) launch_panel<P, (4 * NB <= CAP ? 4 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
-  else launch_panel<P, (8 * NB <= CAP ? 8 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
+  else if (R <= 8 && 8 * NB <= CAP) launch_panel<P, (8 * NB <= CAP ? 8 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
+  else launch_panel<P, (16 * NB <= CAP ? 16 : 1), NB>(c, W, ldw, n, j0, jb, ipiv, info, moved);
 }
 
 template <int P, int R, int NB, bool MF>
@@ -806,13 +816,14 @@ static void panel_gemm_dispatch(Ctx& c, void* W, int ldw, int n, int j0p, int jb
   if (R <= 1) launch_panel_gemm<P, 1, NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
   else if (R <= 2 && 2 * NB <= CAP) launch_panel_gemm<P, (2 * NB <= CAP ? 2 : 1), NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
   else if (R <= 4 && 4 * NB <= CAP) launch_panel_gemm<P, (4 * NB <= CAP ? 4 : 1), NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
-  else launch_panel_gemm<P, (8 * NB <= CAP ? 8 : 1), NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
+  else if (R <= 8 && 8 * NB <= CAP) launch_panel_gemm<P, (8 * NB <= CAP ? 8 : 1), NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
+  else launch_panel_gemm<P, (16 * NB <= CAP ? 16 : 1), NB, MF>(c, W, ldw, n, j0p, jbp, ipiv, info, moved, j0, jb, mtiles);
 }
 
 // LDS of the look-ahead launch: four GEMM tiles plus the panel's exchange buffers.
 template <int P, int NB>
 constexpr bool fuse_fits() {
-  return (PNT / GNT) * 2 * GT * (NB + 4) * sizeof(typename Store<P>::T) +
+  return (PNT / GNT) * 2 * GT * (gemm_k<P, NB>() + 4) * sizeof(typename Store<P>::T) +
              (2 * (PNT / 64) * NB + NB * NB) * sizeof(typename Arith<P>::T) + 1024 <=
          160 * 1024;
 }
@@ -842,14 +853,14 @@ static int getrf_nb(Ctx& c, int n, void* W, int ldw, int* ipiv, int* info, bool 
     const int mt = n - j0 - jb;
     if (mt > 0 && !fuse_fits<P, NB>()) {
       dim3 g((mt + GT - 1) / GT, (mt + GT - 1) / GT);
-      if (mfma) MSIR_TIMED(c, 2, (k_gemm<P, NB, true><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
-      else MSIR_TIMED(c, 2, (k_gemm<P, NB, false><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
+      if (mfma) MSIR_TIMED(c, 2, (k_gemm<P, gemm_k<P, NB>(), true><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
+      else MSIR_TIMED(c, 2, (k_gemm<P, gemm_k<P, NB>(), false><<<g, GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
     } else if (mt > 0) {
       const int mtiles = (mt + GT - 1) / GT;
       const int j1 = j0 + jb, jb1 = (n - j1 < NB) ? n - j1 : NB;
       // tile column 0 of the update (it holds the next panel's columns)
-      if (mfma) MSIR_TIMED(c, 2, (k_gemm<P, NB, true><<<dim3(mtiles, 1), GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
-      else MSIR_TIMED(c, 2, (k_gemm<P, NB, false><<<dim3(mtiles, 1), GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
+      if (mfma) MSIR_TIMED(c, 2, (k_gemm<P, gemm_k<P, NB>(), true><<<dim3(mtiles, 1), GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
+      else MSIR_TIMED(c, 2, (k_gemm<P, gemm_k<P, NB>(), false><<<dim3(mtiles, 1), GNT, 0, c.stream>>>((typename Store<P>::T*)W, ldw, n, j0, jb, 0)));
       if (mtiles > 1) {
         // the next panel and the rest of the update
         if constexpr (fuse_fits<P, NB>()) {
@@ -1100,7 +1111,7 @@ int batch_getrf(Ctx& c, BatchSys* sys, const int* list, int count, int* queue, i
 
 int nb_auto(int n, int prec) {
   const int R = (n + PNT - 1) / PNT;
-  int nb = R <= 1 ? 64 : R <= 2 ? 32 : R <= 4 ? 16 : 8;
+  int nb = R <= 1 ? 64 : R <= 2 ? 32 : R <= 4 ? 16 : R <= 8 ? 8 : 4;
   if (prec == P_FP64) nb /= 2;
   return nb;
 }
@@ -1108,11 +1119,11 @@ int nb_auto(int n, int prec) {
 bool nb_ok(int n, int prec, int nb) {
   const int R = (n + PNT - 1) / PNT;
   const int cap = (prec == P_FP64) ? 32 : 64;
-  int Rp = R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : 8;
-  if (R > 8) return false;
-  if (!(nb == 4 || nb == 8 || nb == 16 || nb == 32 || nb == 64)) return false;
+  int Rp = R <= 1 ? 1 : R <= 2 ? 2 : R <= 4 ? 4 : R <= 8 ? 8 : 16;
+  if (R > 16) return false;
+  if (!(nb == 2 || nb == 4 || nb == 8 || nb == 16 || nb == 32 || nb == 64)) return false;
   if (prec == P_FP64 && nb == 64) return false;
-  if (prec != P_FP64 && nb == 4) return false;
+  if (prec != P_FP64 && nb == 2) return false;
   return Rp * nb <= cap;
 }
 
@@ -1120,6 +1131,7 @@ template <int P>
 static int getrf_p(Ctx& c, int n, void* W, int ldw, int nb, int* ipiv, int* info, bool mf) {
   if constexpr (P == P_FP64) {
     switch (nb) {
+      case 2: return getrf_nb<P, 2>(c, n, W, ldw, ipiv, info, mf);
       case 4: return getrf_nb<P, 4>(c, n, W, ldw, ipiv, info, mf);
       case 8: return getrf_nb<P, 8>(c, n, W, ldw, ipiv, info, mf);
       case 16: return getrf_nb<P, 16>(c, n, W, ldw, ipiv, info, mf);
@@ -1127,6 +1139,7 @@ static int getrf_p(Ctx& c, int n, void* W, int ldw, int nb, int* ipiv, int* info
     }
   } else {
     switch (nb) {
+      case 4: return getrf_nb<P, 4>(c, n, W, ldw, ipiv, info, mf);
       case 8: return getrf_nb<P, 8>(c, n, W, ldw, ipiv, info, mf);
       case 16: return getrf_nb<P, 16>(c, n, W, ldw, ipiv, info, mf);
       case 32: return getrf_nb<P, 32>(c, n, W, ldw, ipiv, info, mf);

@@ -246,7 +246,8 @@ static void launch_arnoldi(Ctx& c, int n, int j, double* V, float* Vf, int ldv, 
   else if (n <= 1024) launch_arnoldi_g<2, 8, 512>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
   else if (n <= 2048) launch_arnoldi_g<4, 8, 512>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
   else if (n <= 4096) launch_arnoldi_g<8, 4, 512>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
-  else launch_arnoldi_g<8, 2, 1024>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else if (n <= 8192) launch_arnoldi_g<8, 2, 1024>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
+  else launch_arnoldi_g<16, 1, 1024>(c, n, j, V, Vf, ldv, w, H, ldh, cs, sn, g, beta0, tau, u, st, mirror);
 }
 
 // y = R^{-1} g (upper triangular from the rotated Hessenberg), one wave,

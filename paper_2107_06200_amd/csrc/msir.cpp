@@ -766,7 +766,7 @@ const char* msir_status_string(int s) {
     case MSIR_ERR_HIP: return g_err[0] ? g_err : "HIP runtime error";
     case MSIR_ERR_TIMEOUT: return "a substitution launch's bounded wait expired";
     case MSIR_ERR_ALLOC: return "device memory could not be allocated within the handle budget";
-    case MSIR_ERR_SIZE: return "n outside [1, 8192]";
+    case MSIR_ERR_SIZE: return "n outside [1, 16384]";
   }
   if (s < 0) return "invalid argument";
   return "unknown status";
@@ -1173,6 +1173,11 @@ static int check_params(int n, const msir_params& P, bool have_xt) {
   }
   if (P.lu_update != MSIR_LU_MFMA && P.lu_update != MSIR_LU_FMA) return -8;
   if (P.gmres_op != MSIR_OP_INVERSE && P.gmres_op != MSIR_OP_SUBST) return -8;
+  // a GMRES cycle's least-squares solve keeps the rotated right-hand side in LDS
+  // (8192 entries): the cycle length is bounded by that for orders above 8192
+  const double kcap = std::min((double)n, ceil(P.k_max > 0 ? P.k_max : 0.1 * n));
+  const double cycle = P.restart > 0 ? std::min((double)P.restart, kcap) : kcap;
+  if (cycle > 8192) return -8;
   return 0;
 }
 

@@ -56,7 +56,7 @@ def test_panel_width_rule_agrees_with_oracle():
     # the oracle and the library state the same default panel-width rule independently
     from paper_2107_06200_amd import msir as M
     from oracle import lu as OLU
-    for n in (1, 64, 100, 1024, 1025, 2048, 3000, 4096, 5000, 8192):
+    for n in (1, 64, 100, 1024, 1025, 2048, 3000, 4096, 5000, 8192, 8193, 12000, 16384):
         for fmt in ("fp16", "bf16", "fp32", "fp64"):
             assert M.nb_auto(n, fmt) == OLU.nb_auto(n, fmt), (n, fmt)
 
