@@ -240,7 +240,9 @@ __device__ __forceinline__ void panel_body(typename Store<P>::T* __restrict__ W,
     for (int s = 0; s < R; ++s) {
       const int r = tid + s * PNT;
       valid[s] = r < m;
-      pos[s] = valid[s] ? r : -1;   // rows past the panel: no position (never c or a pivot)
+      // fp32 search: rows past the panel carry no position (never c or a pivot), so the
+      // tests below need no validity mask
+      pos[s] = (valid[s] || !F32) ? r : -1;
 #pragma unroll
       for (int k = 0; k < NB; ++k) a[s][k] = (valid[s] && k < jb) ? to_a<P>(raw[s][k], AT(0)) : AT(0);
     }
@@ -301,7 +303,7 @@ __device__ __forceinline__ void panel_body(typename Store<P>::T* __restrict__ W,
         int bs = 0;
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-          const K ks = K::make(fabs(a[s][c]), pos[s], pos[s] >= c);
+          const K ks = K::make(fabs(a[s][c]), pos[s], valid[s] && pos[s] >= c);
           if (ks.gt(best)) { best = ks; bs = s; }
         }
         const K wbest = wave_max_key(best);
@@ -341,7 +343,7 @@ __device__ __forceinline__ void panel_body(typename Store<P>::T* __restrict__ W,
       // the row now at position c is final from column c on (its U entries): keep a copy
 #pragma unroll
       for (int s = 0; s < R; ++s)
-        if (pos[s] == c) {
+        if ((F32 || valid[s]) && pos[s] == c) {
 #pragma unroll
           for (int k = c; k < NB; ++k) sU[c][k] = a[s][k];
         }
@@ -353,7 +355,7 @@ __device__ __forceinline__ void panel_body(typename Store<P>::T* __restrict__ W,
         bool act[R];
 #pragma unroll
         for (int s = 0; s < R; ++s) {
-          act[s] = pos[s] > c;
+          act[s] = (F32 || valid[s]) && pos[s] > c;
           l[s] = a_mul(a[s][c], rcp);
           a[s][c] = act[s] ? l[s] : a[s][c];
         }
