@@ -101,17 +101,13 @@ __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict
                                                  double* __restrict__ g, const double* __restrict__ beta0, double tau,
                                                  GStatus* st, GStatus* mirror) {
   static_assert(NT == 256 || NT == 512 || NT == 1024, "4, 8 or 16 wave partials");
-  if (st->done) {
-    if (mirror && threadIdx.x == 0) mirror->done = 1;
-    return;
-  }
   // per-wave partial sums, double-buffered by the parity of the inner-product index
   // so that one barrier per inner product suffices
   __shared__ double sh[2][NT / 64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
-  const double gj = g[j], b0 = *beta0;
-  double* __restrict__ hcol = H + (size_t)j * ldh;
+  // w and the first basis vectors are requested before the status word is tested
+  // (all in bounds), so that their round trips overlap
   int rc[G];
   double w[G];
 #pragma unroll
@@ -121,6 +117,20 @@ __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict
     const double v = w_in[rc[t]];
     w[t] = r < n ? v : 0.0;
   }
+  // the inner products read the basis in the working format (float32 copy unless u is
+  // float64; the values are the same), which halves their memory traffic
+  typedef typename std::conditional<U == P_FP64, double, float>::type VT;
+  const VT* Vr;
+  if constexpr (U == P_FP64) Vr = V; else Vr = Vf;
+  VT B[D][G];
+#pragma unroll
+  for (int d = 0; d < D; ++d) load_col<G>(B[d], Vr, ldv, min(d, j), rc);
+  if (st->done) {
+    if (mirror && threadIdx.x == 0) mirror->done = 1;
+    return;
+  }
+  const double gj = g[j], b0 = *beta0;
+  double* __restrict__ hcol = H + (size_t)j * ldh;
   // the carried entry of the rotation sweep: after step i it is entry i of the column
   // rotated by rotations 0..i-1; entries 0..i-1 are final and stored
   double a = 0.0;
@@ -134,14 +144,6 @@ __global__ __launch_bounds__(NT) void k_arnoldi(int n, int j, double* __restrict
     a = __dadd_rn(__dmul_rn(-si, a), __dmul_rn(ci, h));
     if (tid == 0) hcol[i - 1] = hr;
   };
-  // the inner products read the basis in the working format (float32 copy unless u is
-  // float64; the values are the same), which halves their memory traffic
-  typedef typename std::conditional<U == P_FP64, double, float>::type VT;
-  const VT* Vr;
-  if constexpr (U == P_FP64) Vr = V; else Vr = Vf;
-  VT B[D][G];
-#pragma unroll
-  for (int d = 0; d < D; ++d) load_col<G>(B[d], Vr, ldv, min(d, j), rc);
 #pragma unroll
   for (int i = 0; i < JU; ++i) {
     rotate(i, mgs_step<G, U, NT, TAIL>(n, i, w, B[i % D], sh));
