@@ -456,24 +456,54 @@ __global__ __launch_bounds__(SNT) void k_swap_trsm(typename Store<P>::T* __restr
   if (col >= n) return;
   ST* w = W + (size_t)col * ldw;
   const bool right = col >= jr;
-  // (2) moved values (and A12 from its source rows)
-  ST v[MM];
+  // (2) moved values (and A12 from its source rows).  The moved values wait in LDS, one
+  // column per lane (up to 2 nb of them per column would not fit the registers).
+  // Loads go in batches of 64, all of a batch in flight before any is stored to LDS.
+  constexpr int VB = 64;
+  __shared__ ST sv[MM][SNT];
   AT u[KMAX];
+  for (int i0 = 0; i0 < cnt; i0 += VB) {
+    ST t[VB];
 #pragma unroll
-  for (int i = 0; i < MM; ++i)
-    if (i < cnt) v[i] = w[ssrc[i]];
+    for (int q = 0; q < VB; ++q)
+      if (i0 + q < cnt) t[q] = w[ssrc[i0 + q]];
+#pragma unroll
+    for (int q = 0; q < VB; ++q)
+      if (i0 + q < cnt) sv[i0 + q][tid] = t[q];
+  }
   if (EARLY) {
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) u[k] = (right && k < jb) ? to_a<P>(w[sa12[k]], AT(0)) : AT(0);
   }
+  for (int i0 = 0; i0 < cnt; i0 += VB) {
 #pragma unroll
-  for (int i = 0; i < MM; ++i)
-    if (i < cnt) w[sdst[i]] = v[i];
+    for (int q = 0; q < VB; ++q)
+      if (i0 + q < cnt) w[sdst[i0 + q]] = sv[i0 + q][tid];
+  }
   if (!right) return;
-  if (!EARLY) {
-    // same-thread loads after the stores above see the interchanged values
+  if constexpr (!EARLY) {
+    // 64-wide panels: U12's column is kept in LDS, one column per lane (64 values per
+    // thread in registers were spilled to scratch); same operations in the same order.
+    // Same-thread loads after the stores above see the interchanged values.
+    __shared__ AT su[KMAX][SNT];
+    {
+      ST t[KMAX];   // all loads of the column in flight before the first LDS store
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k) u[k] = (k < jb) ? to_a<P>(w[j0 + k], AT(0)) : AT(0);
+      for (int k = 0; k < KMAX; ++k)
+        if (k < jb) t[k] = w[j0 + k];
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k)
+        if (k < jb) su[k][tid] = to_a<P>(t[k], AT(0));
+    }
+    for (int k = 1; k < jb; ++k) {
+      AT acc = su[k][tid];
+#pragma unroll 8
+      for (int i = 0; i < k; ++i) acc = a_fma(-sL[k][i], su[i][tid], acc);
+      su[k][tid] = acc;
+    }
+#pragma unroll 8
+    for (int k = 0; k < jb; ++k) w[j0 + k] = from_a<P>(su[k][tid]);
+    return;
   }
 #pragma unroll
   for (int k = 1; k < KMAX; ++k) {
